@@ -1,0 +1,175 @@
+"""Epipolar-consistency cost, FP64, one view pair at a time (test
+infrastructure).
+
+Steps, in the paper's order:
+* moved projection P' = P T(theta) and its source (end of "Optimized
+  Algorithm"; "Optimization");
+* pencil of epipolar planes about the baseline, kappa -> E^kappa
+  ("Epipolar Consistency", Eq. 3);
+* epipolar lines without pseudo-inverse, Eqs. 13-14;
+* lookup of the precomputed intermediate function S_lam along each line
+  (Eq. 1, "Epipolar Consistency");
+* d = mean over planes hitting both detectors of (S_a - S_b)^2 (Eq. 15),
+  e = d / (1 + d / c) (Eq. 16), cost = sum over pairs a < b of e (Eq. 17).
+
+Every function is generic over floats and ``Dual`` numbers; ``grad.py``
+differentiates this same code.
+
+Readings (the paper is silent):
+* lookup geometry: line l = (l1, l2, l3) in pixels, centred offset
+  l3c = l3 + l1 u0 + l2 v0, alpha = atan2(l2, l1), t = -l3c / |(l1, l2)|;
+  alpha is folded into [0, pi) with t -> -t and the value negated (odd
+  symmetry of the derivative sinogram);
+* "hits the detector": |t| <= (W/2)|cos alpha| + (H/2)|sin alpha|, the closed
+  rectangle of pixel edges; N_kappa counts planes hitting both detectors and
+  d = 0 when none does;
+* bilinear interpolation in (alpha / dalpha, (t + t_max) / dt) on the floor
+  cell, taps beyond the t grid read as zero, the last alpha row interpolates
+  into the symmetric pad row;
+* S = sign * (1 + t^2 / f^2) * interpolated value (Grangeat's weight on a flat
+  detector, see ``sinogram.py``);
+* pairs a < b only, c = inf meaning e = d.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from .dual import Dual, ops, value
+from .geometry import epipolar_line, epipolar_planes, moved_projection, pencil, plane_angles, source_position
+from .sinogram import SinoGrid
+
+
+@dataclass(frozen=True)
+class EccParams:
+    K: int
+    R_mm: float
+    c: float = math.inf
+
+
+def pair_list(n_views: int):
+    """Pairs (a, b), a < b, in row-major triangle order."""
+    return [(a, b) for a in range(n_views) for b in range(a + 1, n_views)]
+
+
+def pair_index(a: int, b: int, n_views: int) -> int:
+    return a * n_views - a * (a + 1) // 2 + (b - a - 1)
+
+
+def as_rows(P):
+    return [[float(P[i][j]) for j in range(4)] for i in range(3)]
+
+
+def _taps(sino, view, m, k, n_t):
+    ok = (k >= 0) & (k < n_t)
+    out = np.zeros(m.shape, dtype=np.float64)
+    if ok.any():
+        out[ok] = sino.cells(view, m[ok], k[ok])
+    return out
+
+
+def lookup(l, intr, grid: SinoGrid, sino, view):
+    """Value of S_lam along each image line l and whether the line hits the
+    detector.  Returns (S, hit)."""
+    l1, l2, l3 = l
+    f, u0, v0 = (float(x) for x in intr)
+    l3c = l3 + l1 * u0 + l2 * v0
+    r = ops.sqrt(l1 * l1 + l2 * l2)
+    ok = value(r) > 0.0
+    r = ops.where(ok, r, 1.0)
+    alpha = ops.arctan2(l2, l1)
+    t = -l3c / r
+    av = value(alpha)
+    neg = av < 0.0
+    big = av >= math.pi
+    flip = neg | big
+    alpha = ops.where(neg, alpha + math.pi, ops.where(big, alpha - math.pi, alpha))
+    t = ops.where(flip, -t, t)
+    sign = np.where(flip, -1.0, 1.0)
+    av, tv = value(alpha), value(t)
+    hit = ok & (np.abs(tv) <= 0.5 * grid.W * np.abs(np.cos(av)) + 0.5 * grid.H * np.abs(np.sin(av)))
+
+    a = alpha / grid.dalpha
+    m = np.clip(np.floor(value(a)), 0, grid.n_alpha - 1).astype(np.int64)
+    fa = a - m
+    tau = (t + grid.t_max) / grid.dt
+    tau_v = np.where(np.isfinite(value(tau)), value(tau), -10.0)
+    k = np.clip(np.floor(tau_v), -10, grid.n_t + 10).astype(np.int64)
+    ft = tau - k
+    s00 = _taps(sino, view, m, k, grid.n_t)
+    s01 = _taps(sino, view, m, k + 1, grid.n_t)
+    s10 = _taps(sino, view, m + 1, k, grid.n_t)
+    s11 = _taps(sino, view, m + 1, k + 1, grid.n_t)
+    interp = (1.0 - fa) * ((1.0 - ft) * s00 + ft * s01) + fa * ((1.0 - ft) * s10 + ft * s11)
+    weight = 1.0 + t * t / (f * f)
+    S = sign * weight * interp
+    return S, hit
+
+
+def pair_geometry(P_a, P_b, theta_a, theta_b, params: EccParams):
+    """Moved projections, sources, sampled angles, planes and both lines."""
+    Pa = moved_projection(P_a, theta_a)
+    Pb = moved_projection(P_b, theta_b)
+    C_a = source_position(Pa)
+    C_b = source_position(Pb)
+    u1, u2, kappa_max = pencil(C_a, C_b, params.R_mm)
+    kappa = plane_angles(kappa_max, params.K)
+    E = epipolar_planes(u1, u2, C_a, kappa)
+    l_a, _ = epipolar_line(Pa, E)
+    l_b, _ = epipolar_line(Pb, E)
+    return dict(Pa=Pa, Pb=Pb, C_a=C_a, C_b=C_b, u1=u1, u2=u2, kappa_max=kappa_max, kappa=kappa, E=E,
+                l_a=l_a, l_b=l_b)
+
+
+def inconsistency(S_a, S_b, hit):
+    """Eq. 15: d = (1/N) sum over planes hitting both detectors of (S_a - S_b)^2."""
+    N = int(np.count_nonzero(hit))
+    if N == 0:
+        return 0.0, 0
+    diff = S_a - S_b
+    return ops.sum(diff * diff, mask=hit) / float(N), N
+
+
+def robust(d, c):
+    """Eq. 16 (Cauchy): e = d / (1 + d / c); c = inf gives e = d."""
+    if math.isinf(c):
+        return d
+    return d / (1.0 + d / c)
+
+
+def ecc_pair(P_a, P_b, theta_a, theta_b, intr_a, intr_b, grid: SinoGrid, sino, a, b, params: EccParams):
+    """(e_ab, d_ab, N_kappa) for one view pair."""
+    g = pair_geometry(P_a, P_b, theta_a, theta_b, params)
+    S_a, hit_a = lookup(g["l_a"], intr_a, grid, sino, a)
+    S_b, hit_b = lookup(g["l_b"], intr_b, grid, sino, b)
+    d, N = inconsistency(S_a, S_b, hit_a & hit_b)
+    return robust(d, params.c), d, N
+
+
+def ecc_cost(P, intr, theta, grid: SinoGrid, sino, params: EccParams, pairs=None):
+    """Total cost (Eq. 17's sum over a < b) for one motion hypothesis theta
+    [N, 6] and the per-pair (e, d, N) arrays, in ``pairs`` order (default: all
+    pairs, row-major triangle)."""
+    n = len(P)
+    if pairs is None:
+        pairs = pair_list(n)
+    e = np.zeros(len(pairs))
+    d = np.zeros(len(pairs))
+    N = np.zeros(len(pairs), dtype=np.int64)
+    for i, (a, b) in enumerate(pairs):
+        ei, di, Ni = ecc_pair(as_rows(P[a]), as_rows(P[b]), [float(x) for x in theta[a]],
+                              [float(x) for x in theta[b]], intr[a], intr[b], grid, sino, a, b, params)
+        e[i], d[i], N[i] = float(value(ei)), float(value(di)), Ni
+    return float(e.sum()), e, d, N
+
+
+def ecc_pair_grad(P_a, P_b, theta_a, theta_b, intr_a, intr_b, grid, sino, a, b, params: EccParams):
+    """e_ab and its exact derivative w.r.t. (theta_a, theta_b) (12 values)."""
+    ta = [Dual.variable(theta_a[i], i, 12) for i in range(6)]
+    tb = [Dual.variable(theta_b[i], 6 + i, 12) for i in range(6)]
+    e, _, _ = ecc_pair(P_a, P_b, ta, tb, intr_a, intr_b, grid, sino, a, b, params)
+    if not isinstance(e, Dual):
+        return float(e), np.zeros(12)
+    return float(e.v), np.array(e.d, dtype=np.float64)

@@ -1,0 +1,169 @@
+"""Projective-geometry steps of the method, FP64, written out component by
+component (test infrastructure; generic over floats, NumPy arrays and
+``Dual`` so the same code yields exact derivatives).
+
+Objects are plain Python sequences: a plane or point is 4 scalars, a line is
+the 6 Pluecker coordinates (p, q, r, s, t, u), matrices are lists of rows.
+Each scalar may be a float, an array (one entry per sampled plane) or a Dual.
+
+Readings of the paper taken here (it is silent or inconsistent):
+* Eq. 5 as printed puts -p in row 0 and +p in row 1; with (p..u) from Eq. 4
+  that matrix does not annihilate the two planes the line came from.  The
+  matrix used is the one that does: row 0 = (0, p, -q, r), row 1 =
+  (-p, 0, s, -t), rows 2-3 as printed.
+* Rigid motion: T(theta) = [[Rz(rz) Ry(ry) Rx(rx), (tx, ty, tz)], [0, 1]],
+  angles in degrees, applied as P' = P T (the composition P_lam T_lam of the
+  "Optimization" subsection).
+"""
+from __future__ import annotations
+
+import math
+
+from .dual import ops
+
+PLANE_AT_INFINITY = (0.0, 0.0, 0.0, 1.0)  # the plane pi_inf of the "Projective Geometry" subsection
+
+
+def meet(a, b):
+    """Eq. 4: Pluecker coordinates of the line common to planes a and b."""
+    ax, ay, az, aw = a
+    bx, by, bz, bw = b
+    p = az * bw - aw * bz
+    q = ay * bw - aw * by
+    r = ay * bz - az * by
+    s = ax * bw - aw * bx
+    t = ax * bz - az * bx
+    u = ax * by - ay * bx
+    return (p, q, r, s, t, u)
+
+
+def plucker_matrix(L):
+    """Eq. 5 (sign of the p entries corrected, see module header): the 4x4
+    antisymmetric L_K whose product with a plane is the point where the line
+    pierces that plane."""
+    p, q, r, s, t, u = L
+    return [
+        [0.0, p, -q, r],
+        [-p, 0.0, s, -t],
+        [q, -s, 0.0, u],
+        [-r, t, -u, 0.0],
+    ]
+
+
+def matvec(M, x):
+    return [sum(M[i][j] * x[j] for j in range(len(x))) for i in range(len(M))]
+
+
+def matmul(A, B):
+    n, k, m = len(A), len(B), len(B[0])
+    return [[sum(A[i][j] * B[j][c] for j in range(k)) for c in range(m)] for i in range(n)]
+
+
+def transpose(A):
+    return [[A[i][j] for i in range(len(A))] for j in range(len(A[0]))]
+
+
+def meet_line_plane(L, plane):
+    """Eq. 5: point common to line L and a plane, x = L_K p."""
+    return matvec(plucker_matrix(L), plane)
+
+
+def motion_matrix(theta):
+    """4x4 rigid transform T(theta), theta = (rx, ry, rz [deg], tx, ty, tz [mm])."""
+    rx, ry, rz = (theta[i] * (math.pi / 180.0) for i in range(3))
+    cx, sx = ops.cos(rx), ops.sin(rx)
+    cy, sy = ops.cos(ry), ops.sin(ry)
+    cz, sz = ops.cos(rz), ops.sin(rz)
+    Rx = [[1.0, 0.0, 0.0], [0.0, cx, -sx], [0.0, sx, cx]]
+    Ry = [[cy, 0.0, sy], [0.0, 1.0, 0.0], [-sy, 0.0, cy]]
+    Rz = [[cz, -sz, 0.0], [sz, cz, 0.0], [0.0, 0.0, 1.0]]
+    Rm = matmul(Rz, matmul(Ry, Rx))
+    return [
+        [Rm[0][0], Rm[0][1], Rm[0][2], theta[3]],
+        [Rm[1][0], Rm[1][1], Rm[1][2], theta[4]],
+        [Rm[2][0], Rm[2][1], Rm[2][2], theta[5]],
+        [0.0, 0.0, 0.0, 1.0],
+    ]
+
+
+def moved_projection(P, theta):
+    """P' = P T(theta) ("Optimization" subsection)."""
+    return matmul(P, motion_matrix(theta))
+
+
+def source_position(P):
+    """Source of a 3x4 projection matrix (end of the "Optimized Algorithm"
+    subsection): the rows of P are planes through the source; the line where
+    rows 0 and 1 meet (Eq. 4) pierces row 2 (Eq. 5) at the source.  Returned
+    dehomogenised (3 components)."""
+    L = meet(P[0], P[1])
+    X = meet_line_plane(L, P[2])
+    return [X[0] / X[3], X[1] / X[3], X[2] / X[3]]
+
+
+def dot3(a, b):
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]
+
+
+def cross3(a, b):
+    return [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]
+
+
+def _value(x):
+    return x.v if hasattr(x, "v") else x
+
+
+def pencil(C_a, C_b, R_mm):
+    """Pencil of epipolar planes about the baseline C_a C_b (the angle ->
+    plane mapping of the "Epipolar Consistency" subsection, whose basis and
+    range the paper leaves open).  Returns (u1, u2, kappa_max):
+    n(kappa) = cos(kappa) u1 + sin(kappa) u2 is the unit normal of the plane
+    at angle kappa; u2 points from the baseline towards the isocentre, so the
+    plane lies h |sin kappa| from the isocentre (h = baseline-isocentre
+    distance) and the planes meeting the object sphere of radius R_mm are
+    |kappa| <= asin(min(1, R/h))."""
+    b = [C_b[i] - C_a[i] for i in range(3)]
+    nb = ops.sqrt(dot3(b, b))
+    bh = [b[i] / nb for i in range(3)]
+    ca_b = dot3(C_a, bh)
+    w = [-C_a[i] + ca_b * bh[i] for i in range(3)]
+    h = ops.sqrt(dot3(w, w))
+    if float(_value(h)) < 1e-9:
+        bv = [float(_value(x)) for x in bh]
+        ax = min(range(3), key=lambda i: abs(bv[i]))
+        e = [1.0 if i == ax else 0.0 for i in range(3)]
+        eb = dot3(e, bh)
+        w = [e[i] - eb * bh[i] for i in range(3)]
+        nw = ops.sqrt(dot3(w, w))
+        u2 = [w[i] / nw for i in range(3)]
+        kappa_max = math.pi / 2
+    else:
+        u2 = [w[i] / h for i in range(3)]
+        ratio = R_mm / h
+        kappa_max = ops.arcsin(ratio) if float(_value(ratio)) < 1.0 else math.pi / 2
+    u1 = cross3(bh, u2)
+    return u1, u2, kappa_max
+
+
+def plane_angles(kappa_max, K):
+    """Midpoint sampling of [-kappa_max, kappa_max] with K planes,
+    kappa_k = -kappa_max + (k + 1/2) * 2 kappa_max / K, k = 0..K-1 (Eq. 15's
+    sum read as K terms)."""
+    import numpy as np
+
+    frac = (np.arange(K, dtype=np.float64) + 0.5) * (2.0 / K) - 1.0
+    return kappa_max * frac
+
+
+def epipolar_planes(u1, u2, C_a, kappa):
+    """E^kappa = (n, -n . C_a) for every sampled angle (homogeneous planes)."""
+    c, s = ops.cos(kappa), ops.sin(kappa)
+    n = [c * u1[i] + s * u2[i] for i in range(3)]
+    return [n[0], n[1], n[2], -dot3(n, C_a)]
+
+
+def epipolar_line(P, E):
+    """Eqs. 13-14: L = meet(E, pi_inf); [l]_x = P L_K P^T; l = (S12, S20, S01)."""
+    L = meet(E, PLANE_AT_INFINITY)
+    S = matmul(matmul(P, plucker_matrix(L)), transpose(P))
+    return [S[1][2], S[2][0], S[0][1]], S

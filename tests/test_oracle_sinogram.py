@@ -1,0 +1,184 @@
+"""Pins of the oracle's Radon-derivative sinogram (Eq. 1 on a flat detector)
+against closed forms: the trapezoid-exact integral of a constant image, the
+exact integral of the bilinear interpolant along a line, the closed-form 3-D
+Radon derivative of a sphere and of ellipsoids, and the odd symmetry of the
+pad row."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.sinogram import SinoGrid, cosine_weighted, drho_cells, full_sinogram, line_integrals
+from paper_1806_02637_amd import inputs
+
+
+def test_constant_image_line_integrals_are_exact():
+    # For a constant image c the bilinear interpolant is c on [0, W-1] and
+    # ramps linearly to 0 over the one-pixel border; with the samples on the
+    # half-pixel lattice (u0, v0 half-integers, ds = 0.5) the sum is the
+    # trapezoid rule of a piecewise-linear function, i.e. exact: c * H for
+    # vertical lines, c * W for horizontal ones.
+    W, H, c = 40, 24, 2.5
+    grid = SinoGrid(W, H, 2, 31, 0.5)
+    img = np.full((H, W), c)
+    u0, v0 = (W - 1) / 2, (H - 1) / 2
+    k = np.arange(grid.n_t)
+    t = -grid.t_max + k * grid.dt
+    G0 = line_integrals(img, grid, u0, v0, np.zeros_like(k), k)  # alpha = 0: x = u0 + t
+    inside = (u0 + t >= 0) & (u0 + t <= W - 1)
+    assert inside.sum() > 10
+    assert np.allclose(G0[inside], c * H, rtol=1e-13)
+    G90 = line_integrals(img, grid, u0, v0, np.ones_like(k), k)  # alpha = pi/2: y = v0 + t
+    inside = (v0 + t >= 0) & (v0 + t <= H - 1)
+    assert np.allclose(G90[inside], c * W, rtol=1e-12)
+
+
+def _exact_bilinear_line_integral(img, u0, v0, alpha, t, s_lo, s_hi):
+    """Integral over s in [s_lo, s_hi] of the bilinear interpolant (zero
+    outside the image) along x = u0 + t cos a - s sin a, y = v0 + t sin a + s cos a:
+    split at every crossing of an integer grid line, where the integrand is a
+    quadratic in s, and integrate each piece with Simpson's rule (exact)."""
+    H, W = img.shape
+    ca, sa = math.cos(alpha), math.sin(alpha)
+
+    def point(s):
+        return u0 + t * ca - s * sa, v0 + t * sa + s * ca
+
+    def f(s):
+        x, y = point(s)
+        i0, j0 = math.floor(x), math.floor(y)
+        fx, fy = x - i0, y - j0
+        acc = 0.0
+        for di, dj, wgt in ((0, 0, (1 - fx) * (1 - fy)), (1, 0, fx * (1 - fy)), (0, 1, (1 - fx) * fy), (1, 1, fx * fy)):
+            i, j = i0 + di, j0 + dj
+            if 0 <= i < W and 0 <= j < H:
+                acc += wgt * img[j, i]
+        return acc
+
+    cuts = {s_lo, s_hi}
+    for coord0, dcoord in ((u0 + t * ca, -sa), (v0 + t * sa, ca)):
+        if abs(dcoord) > 1e-15:
+            for g in range(-3, max(W, H) + 3):
+                s = (g - coord0) / dcoord
+                if s_lo < s < s_hi:
+                    cuts.add(s)
+    cuts = sorted(cuts)
+    total = 0.0
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        total += (b - a) / 6.0 * (f(a) + 4 * f(0.5 * (a + b)) + f(b))
+    return total
+
+
+def test_line_sum_converges_to_exact_bilinear_integral(rng):
+    W, H = 9, 7
+    img = rng.uniform(0.0, 1.0, (H, W))
+    u0, v0 = (W - 1) / 2, (H - 1) / 2
+    errs = {}
+    for ds in (0.01, 0.005):
+        grid = SinoGrid(W, H, 12, 15, ds)
+        ms = np.array([0, 1, 3, 5, 7, 10, 11])
+        ks = np.array([3, 7, 5, 9, 6, 2, 11])
+        G = line_integrals(img, grid, u0, v0, ms, ks)
+        half = 0.5 * (grid.n_s - 1) * ds
+        ref = np.array([_exact_bilinear_line_integral(img, u0, v0, m * grid.dalpha, -grid.t_max + k * grid.dt,
+                                                      -half - 0.5 * ds, half + 0.5 * ds) for m, k in zip(ms, ks)])
+        errs[ds] = np.abs(G - ref).max() / np.abs(ref).max()
+    assert errs[0.005] < 1e-4
+    assert errs[0.005] < 0.5 * errs[0.01]  # converges (O(ds^2) at kinks)
+
+
+def test_pad_row_equals_direct_evaluation_at_pi(small16):
+    # stored row n_alpha uses the odd symmetry; evaluate the line integral at
+    # alpha = pi directly and difference it the same way
+    g, grid, imgs, intr = small16["geom"], small16["grid"], small16["images"], small16["intr"]
+    f, u0, v0 = intr[3]
+    gw = cosine_weighted(imgs[3], f, u0, v0)
+    k = np.arange(grid.n_t)
+    G = line_integrals(gw, grid, u0, v0, np.full_like(k, grid.n_alpha), k)
+    Gp = np.concatenate([[0.0], G, [0.0]])
+    direct = (Gp[2:] - Gp[:-2]) / (2 * grid.dt)
+    stored = small16["sino"].data[3, grid.n_alpha]
+    assert np.allclose(stored, direct, rtol=1e-9, atol=1e-9 * np.abs(direct).max())
+    # and the lazy cell evaluation agrees with the full build everywhere it is asked
+    mm = np.array([0, 5, 90, 179, 180, 180])
+    kk = np.array([0, 50, 90, 180, 3, 177])
+    lazy = drho_cells(gw, grid, u0, v0, mm, kk)
+    assert np.allclose(lazy, small16["sino"].data[3][mm, kk], rtol=1e-12, atol=1e-12)
+
+
+def _camera_normals(grid, f, R):
+    al = np.arange(grid.n_alpha) * grid.dalpha
+    t = -grid.t_max + np.arange(grid.n_t) * grid.dt
+    A, T = np.meshgrid(al, t, indexing="ij")
+    n = np.stack([f * np.cos(A), f * np.sin(A), -T], -1)
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    return n @ R, T  # world normal = R^T n_cam
+
+
+def _ellipsoid_radon_derivative(ph, n, d, dd_margin):
+    """Closed form d/dd of the plane integral of an ellipsoid sum: with
+    sigma = |diag(a) Q^T n| and d' = d - n.x_e, R f = rho pi a1 a2 a3 (1 - (d'/sigma)^2) / sigma
+    for |d'| < sigma, so dR f/dd = -2 pi rho a1 a2 a3 d' / sigma^3 there.  Also flags
+    cells within dd_margin of a tangency (|d'| = sigma), where the derivative jumps."""
+    out = np.zeros(d.shape)
+    near = np.zeros(d.shape, bool)
+    for e in range(ph.n):
+        a, Q = ph.semi_axes[e], ph.axes[e]
+        sig = np.linalg.norm((n @ Q) * a, axis=-1)
+        dp = d - n @ ph.centers[e]
+        inside = np.abs(dp) < sig
+        out += np.where(inside, -2 * math.pi * ph.density[e] * a.prod() * dp / sig ** 3, 0.0)
+        near |= np.abs(np.abs(dp) - sig) < dd_margin
+    return out, near
+
+
+def test_sphere_matches_closed_form_with_grangeat_weight():
+    # homogeneous sphere (radius rho_s, density mu) at the isocentre:
+    # dR f/dd = -2 pi mu d for |d| < rho_s with d = SID t / sqrt(f^2 + t^2);
+    # wide cone (t/f up to 0.26) so the (1 + t^2/f^2) factor matters
+    geom = inputs.ScanGeometry(4, 256, 256, 2.4)
+    rho_s, mu = 150.0, 0.5
+    img = inputs.project(geom, inputs.sphere_phantom(rho_s, mu), views=[0])[0]
+    grid = SinoGrid(256, 256, 36, 301)
+    f = geom.f_px
+    sino = full_sinogram(img, grid, f, geom.u0, geom.v0)[:grid.n_alpha]
+    t = -grid.t_max + np.arange(grid.n_t) * grid.dt
+    d = geom.sid_mm * t / np.sqrt(f * f + t * t)
+    ref = -2 * math.pi * mu * d * (np.abs(d) < rho_s)
+    ok = (np.abs(np.abs(d) - rho_s) > 4 * grid.dt * geom.pitch_mm) & (np.abs(t) < 128)
+    refb = np.broadcast_to(ref, sino.shape)[:, ok]
+    weighted = (1 + t ** 2 / f ** 2)[None, :] * sino
+    err_w = np.linalg.norm((weighted[:, ok] - refb)) / np.linalg.norm(refb)
+    err_u = np.linalg.norm((sino[:, ok] - refb)) / np.linalg.norm(refb)
+    assert err_w < 0.01
+    assert err_u > 0.015  # the test sees a missing weight
+    # isotropy: a centred sphere's sinogram does not depend on alpha
+    assert np.abs(sino - sino.mean(0)).max() < 0.03 * np.abs(sino).max()
+
+
+@pytest.mark.slow
+def test_ellipsoids_converge_to_closed_form_radon_derivative():
+    # FOV-contained 10-ellipsoid phantom (seed 1): (1 + t^2/f^2) d rho against
+    # the closed form at n = world normal of the plane through source and
+    # detector line, d = n . C; error must shrink under detector refinement.
+    w = inputs.WORKLOADS["small16"]
+    ph = w.phantom(contained=True)
+    errs = []
+    for scale in (1, 2):
+        geom = inputs.ScanGeometry(4, 128 * scale, 128 * scale, 2.4 / scale)
+        grid = SinoGrid(geom.W, geom.H, 60, 91 * scale)
+        C, R = geom.frames()
+        imgs = inputs.project(geom, ph, views=[0, 1])
+        e = []
+        for v in (0, 1):
+            sino = full_sinogram(imgs[v], grid, geom.f_px, geom.u0, geom.v0)[:grid.n_alpha]
+            n, T = _camera_normals(grid, geom.f_px, R[v])
+            d = n @ C[v]
+            ref, near = _ellipsoid_radon_derivative(ph, n, d, 2 * grid.dt * geom.pitch_mm)
+            S = (1 + T ** 2 / geom.f_px ** 2) * sino
+            e.append(np.linalg.norm((S - ref)[~near]) / np.linalg.norm(ref[~near]))
+            assert np.sum(S * ref) > 0.97 * np.linalg.norm(S) * np.linalg.norm(ref)  # sign
+        errs.append(max(e))
+    assert errs[0] < 0.015
+    assert errs[1] < 0.01
+    assert errs[1] < 0.8 * errs[0]
