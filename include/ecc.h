@@ -1,0 +1,164 @@
+/*
+ * ecc.h -- C ABI of the MI355X engine for Grangeat-based epipolar consistency
+ * (ECC) of C-arm cone-beam projections (arxiv 1806.02637, "Fast Epipolar
+ * Consistency without the Need for Pseudo Matrix Inverses").
+ *
+ * The engine holds scans (views + 3x4 projection matrices), builds each view's
+ * Radon-derivative sinogram once and keeps it in HBM, and evaluates the
+ * consistency cost (and its gradient) for batches of per-view rigid-motion
+ * hypotheses.  All compute runs in HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns ecc_status: ECC_OK (0) or a negative code.  No
+ *   function aborts.  The message of the last failure on the calling thread
+ *   is available from ecc_last_error().
+ * - Argument checks (shapes, ranges, NULLs, unknown ids) are synchronous and
+ *   leave no partial state.  HIP failures are reported as ECC_E_HIP.
+ * - Pointers named *_dev are device pointers on the context's device; the
+ *   caller keeps ownership and must keep them alive until the work queued on
+ *   `stream` has completed.  Host pointers are only read during the call.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Evaluation entry points are asynchronous on that stream.
+ * - A context may be used from several host threads; scan loading/freeing is
+ *   serialised internally.  Evaluations on different streams may overlap on
+ *   the device as long as each has its own workspace.
+ * - Pairs are the N(N-1)/2 view pairs a < b in row-major triangle order:
+ *   pair index p(a, b) = a N - a (a + 1) / 2 + (b - a - 1).
+ */
+#ifndef ECC_H
+#define ECC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ecc_status;
+typedef struct ecc_ctx ecc_ctx;
+
+enum {
+    ECC_OK = 0,
+    ECC_E_ARG = -1,     /* invalid argument, shape or value */
+    ECC_E_BUDGET = -2,  /* the request would exceed the context's HBM budget */
+    ECC_E_HIP = -3,     /* a HIP runtime call failed */
+    ECC_E_STATE = -4,   /* call out of order (e.g. cost before sinograms are built) */
+    ECC_E_NOSCAN = -5   /* unknown or freed scan id */
+};
+
+/* Storage type of the resident sinograms. */
+enum { ECC_F32 = 0, ECC_BF16 = 1, ECC_F16 = 2 };
+
+/* Precision of the per-plane geometry (epipolar line, its angle and offset).
+ * The per-view and per-pair geometry (moved projection, sources, baseline,
+ * pencil of planes) is always FP64. */
+enum { ECC_GEOM_F32 = 0, ECC_GEOM_F64 = 1 };
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ecc_last_error(void);
+
+/* Creates a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds
+ * the device memory the context itself allocates (resident scans); 0 means
+ * no bound. */
+ecc_status ecc_create(ecc_ctx **out, int hip_device, uint64_t hbm_budget_bytes);
+
+/* Frees every scan and the context.  Waits for the device to go idle. */
+ecc_status ecc_destroy(ecc_ctx *ctx);
+
+/* Loads one scan ("a configuration of ... projections described by their
+ * projection matrix", Sec. "Epipolar Consistency").
+ *   P      [n_views][3][4] FP64, row-major, maps world mm to detector pixels
+ *          (pixel centres at integer (u, v), u = column, v = row).  All views
+ *          must share the sign of det(P[:, :3]) (one detector handedness).
+ *   intr   [n_views][3] FP64 = {f_px, u0, v0}: focal length in pixels and the
+ *          principal point, used for the cosine weight of Eq. 1 and to centre
+ *          detector lines.  Rigid motion does not change them.
+ *   images [n_views][H][W] FP32 line integrals (row v, column u); host memory
+ *          if images_on_device == 0, else a device pointer.  Copied.
+ * The projections are held (FP32, in HBM) until sinograms are built.
+ * Errors: ECC_E_ARG (sizes < 2, NULLs, non-finite or mixed-handedness P),
+ * ECC_E_BUDGET, ECC_E_HIP. */
+ecc_status ecc_scan_load(ecc_ctx *ctx, int32_t *scan_id, int32_t n_views, int32_t W, int32_t H,
+                         const double *P, const double *intr, const float *images, int32_t images_on_device);
+
+/* Builds every view's Radon-derivative sinogram: Grangeat's intermediate
+ * function (Eq. 1) on a flat detector, precomputed once per projection
+ * (Sec. "Epipolar Consistency").  Grid: alpha_m = m pi / n_alpha,
+ * t_k = -t_max + k 2 t_max / (n_t - 1), t_max = sqrt(W^2 + H^2) / 2 px; line
+ * integrals of the cosine-weighted image sampled every ds_px pixels with
+ * bilinear interpolation; stored value = central t-difference of the line
+ * integrals.  dtype selects the storage (ECC_F32 / ECC_BF16 / ECC_F16; FP16
+ * is stored with an exact per-view power-of-two scale).  Runs on `stream`
+ * and synchronises it before returning; the projections are then released.
+ * Errors: ECC_E_ARG (n_alpha < 2, n_t < 3, ds_px <= 0, bad dtype),
+ * ECC_E_STATE (already built), ECC_E_NOSCAN, ECC_E_BUDGET, ECC_E_HIP. */
+ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t,
+                                    double ds_px, int32_t dtype, void *stream);
+
+/* Installs sinograms computed elsewhere instead of building them (same grid
+ * as above).  sino: [n_views][n_alpha + 1][n_t] FP32, row n_alpha holding
+ * the values at alpha = pi, host memory (sino_on_device == 0) or device.
+ * Converted to `dtype` on the device.  Errors as ecc_scan_build_sinograms. */
+ecc_status ecc_scan_set_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t,
+                                  const float *sino, int32_t sino_on_device, int32_t dtype);
+
+/* Copies one view's resident sinogram back, decoded to FP32, as
+ * [n_alpha + 1][n_t] into host memory `out` (synchronous). */
+ecc_status ecc_scan_read_sinogram(ecc_ctx *ctx, int32_t scan_id, int32_t view, float *out);
+
+/* Releases a scan and its device memory (after the device is idle). */
+ecc_status ecc_scan_free(ecc_ctx *ctx, int32_t scan_id);
+
+/* Device bytes the scan holds now. */
+ecc_status ecc_scan_bytes(ecc_ctx *ctx, int32_t scan_id, uint64_t *bytes);
+
+/* Evaluation parameters.
+ *   K     number of epipolar planes sampled per pair (Eq. 15), 1..4096;
+ *   R_mm  radius of the isocentric object sphere: the pencil of planes about
+ *         the baseline C_a C_b is sampled over the angles whose planes meet
+ *         that sphere, kappa_k = -kappa_max + (k + 1/2) 2 kappa_max / K with
+ *         kappa_max = asin(min(1, R_mm / h)), h = baseline-isocentre distance;
+ *   c     Cauchy parameter of Eq. 16 (c <= 0 or infinite means e = d);
+ *   geom  ECC_GEOM_F32 or ECC_GEOM_F64 (per-plane geometry precision). */
+typedef struct {
+    int32_t K;
+    int32_t geom;
+    double R_mm;
+    double c;
+} ecc_eval_params;
+
+/* Device workspace (bytes) an evaluation of B hypotheses needs; with_grad
+ * selects ecc_cost_grad. */
+ecc_status ecc_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, int32_t B, int32_t with_grad, uint64_t *bytes);
+
+/* Cost of Eq. 17 for B motion hypotheses (Sec. "Optimization"):
+ *   theta_dev    [B][n_views][6] FP64 {rx, ry, rz [deg], tx, ty, tz [mm]};
+ *                view lam is evaluated with P_lam T(theta), T = [[Rz Ry Rx, t], [0, 1]];
+ *   out_cost_dev [B] FP64: sum over pairs a < b of e_ab (Eqs. 15-16);
+ *   out_pair_dev [B][n_pairs] FP32 per-pair e_ab, or NULL;
+ *   workspace_dev, workspace_bytes: scratch of at least ecc_workspace_bytes.
+ * Results are deterministic (fixed reduction order, no atomics).
+ * Errors: ECC_E_ARG, ECC_E_NOSCAN, ECC_E_STATE (no sinograms), ECC_E_HIP. */
+ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                    const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
+                    void *workspace_dev, uint64_t workspace_bytes, void *stream);
+
+/* Cost and its gradient with respect to every view's 6 motion parameters
+ * (reverse sweep through Eqs. 13-16; the line geometry is recomputed, not
+ * stored).  grad_dev [B][n_views][6] FP32 is overwritten.
+ * out_pair_grad_dev [B][n_pairs][12] FP32 (d e_ab / d theta_a, then
+ * d e_ab / d theta_b) or NULL.  Other arguments as ecc_cost. */
+ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                         const ecc_eval_params *params, double *out_cost_dev, float *grad_dev,
+                         float *out_pair_grad_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream);
+
+/* Number of views / pairs and the sinogram grid of a scan (any may be NULL). */
+ecc_status ecc_scan_info(ecc_ctx *ctx, int32_t scan_id, int32_t *n_views, int32_t *n_pairs, int32_t *n_alpha,
+                         int32_t *n_t, int32_t *dtype);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECC_H */

@@ -1,0 +1,251 @@
+// Adjoint of the consistency cost: d cost / d theta for every view's six
+// motion parameters, with the line geometry recomputed rather than stored.
+//
+// ecc_adj      same work split as the forward kernel (4 hypotheses x one
+//              64-pair tile per workgroup).  Per pair:
+//                1. forward sweep over the K planes -> d, N (Eq. 15), e (Eq. 16);
+//                2. reverse sweep over the planes: dE/dS_a = +g, dE/dS_b = -g with
+//                   g = de/dd * 2 (S_a - S_b) / N on planes hitting both
+//                   detectors; through the weighted bilinear lookup to
+//                   (alpha, t), through atan2 / offset to the line l, through
+//                   l = H (cos k, sin k) to the 6 + 6 line-map entries and to
+//                   kappa_max (k = kappa_max ((2k+1)/K - 1)); wave-shuffle sum
+//                   of those 13 sensitivities, kept by lane (pair % 64);
+//              then every lane owns one pair and runs 12 FP64 forward-mode
+//              (dual number) sweeps of the per-pair geometry -- one per motion
+//              parameter of views a and b, seeded with dP'/dtheta -- and
+//              contracts them with the 13 sensitivities.
+// reduce_grad  fixed-order sum of the per-pair 12-vectors into grad[B][N][6].
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ecc_internal.hpp"
+#include "lookup.hpp"
+#include "pair.hpp"
+#include "projective.hpp"
+
+namespace ecc {
+
+// Reverse sweep through one view's lookup: accumulates dE/dH (6) and the
+// plane-angle derivative dE/dkappa_k given gS = dE/dS.
+template <class Tap, class G>
+__device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const Tap *sview, const EvalConsts &ec,
+                                               float inv_f2, float scale, float gS, const LineCoord<G> &c,
+                                               float gH[6], float &gk) {
+    const Taps tp = Tap::load(sview + (int64_t)c.m * ec.row_elems + (c.k + 1));
+    const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
+    const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
+    const float Bv = fmaf(c.fa, r1 - r0, r0);
+    const float w = fmaf(c.tf * c.tf, inv_f2, 1.0f);
+    const float dB_da = (r1 - r0) * ec.inv_dalpha;
+    const float dB_dt = fmaf(c.fa, (tp.s11 - tp.s10) - (tp.s01 - tp.s00), tp.s01 - tp.s00) * ec.inv_dt;
+    // S = sgn * scale * w(t_f) * B(alpha_f, t_f), t_f = sgn * t_raw
+    const float dS_dalpha = c.sgn * scale * w * dB_da;
+    const float dS_dt = scale * (2.0f * c.tf * inv_f2 * Bv + w * dB_dt);
+    const float l1 = (float)c.l1, l2 = (float)c.l2, l3 = (float)c.l3;
+    const float rinv = (float)c.rinv;
+    const float rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
+    // alpha = atan2(l2, l1), t_raw = -l3 / r
+    const float gl1 = gS * (dS_dalpha * (-l2 * rinv2) + dS_dt * (l3 * l1 * rinv3));
+    const float gl2 = gS * (dS_dalpha * (l1 * rinv2) + dS_dt * (l3 * l2 * rinv3));
+    const float gl3 = gS * (dS_dt * (-rinv));
+    const float fc = (float)cs, fs = (float)sn;
+    gH[0] = fmaf(gl1, fc, gH[0]);
+    gH[1] = fmaf(gl2, fc, gH[1]);
+    gH[2] = fmaf(gl3, fc, gH[2]);
+    gH[3] = fmaf(gl1, fs, gH[3]);
+    gH[4] = fmaf(gl2, fs, gH[4]);
+    gH[5] = fmaf(gl3, fs, gH[5]);
+    // dl/dkappa = H (-sin, cos)
+    gk += gl1 * ((float)h[3] * fc - (float)h[0] * fs) + gl2 * ((float)h[4] * fc - (float)h[1] * fs) +
+          gl3 * ((float)h[5] * fc - (float)h[2] * fs);
+}
+
+// Directional derivative of (Ha, Hb, kappa_max) along one motion parameter,
+// contracted with the sensitivities g13 = (dE/dHa [6], dE/dHb [6], dE/dkappa_max).
+__device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const ViewGeomGrad &gA,
+                               const ViewGeomGrad &gB, int dir, double R_mm, const float g13[13]) {
+    Dual Pa[12], Pb[12], Ca[3], Cb[3];
+    const bool on_a = dir < 6;
+    const int q = on_a ? dir : dir - 6;
+    for (int e = 0; e < 12; ++e) {
+        Pa[e] = Dual(A.P[e], on_a ? gA.dP[q][e] : 0.0);
+        Pb[e] = Dual(Bv.P[e], on_a ? 0.0 : gB.dP[q][e]);
+    }
+    for (int e = 0; e < 3; ++e) {
+        Ca[e] = Dual(A.C[e], on_a ? gA.dC[q][e] : 0.0);
+        Cb[e] = Dual(Bv.C[e], on_a ? 0.0 : gB.dC[q][e]);
+    }
+    Dual u1[3], u2[3], km;
+    pencil(Ca, Cb, R_mm, u1, u2, km);
+    Dual Ha[6], Hb[6];
+    line_map(Pa, Ca, u1, u2, A.u0, A.v0, Ha);
+    line_map(Pb, Ca, u1, u2, Bv.u0, Bv.v0, Hb);
+    // the forward pass scaled each map by an exact power of two (the same
+    // exponent follows from the values here); sensitivities were taken with
+    // respect to the scaled maps
+    double ma = 0.0, mb = 0.0;
+    for (int i = 0; i < 6; ++i) {
+        ma = fmax(ma, fabs(Ha[i].v));
+        mb = fmax(mb, fabs(Hb[i].v));
+    }
+    const int ea = ma > 0.0 ? ilogb(ma) : 0, eb = mb > 0.0 ? ilogb(mb) : 0;
+    double ga = 0.0, gb = 0.0;
+    for (int i = 0; i < 6; ++i) {
+        ga += (double)g13[i] * Ha[i].d;
+        gb += (double)g13[6 + i] * Hb[i].d;
+    }
+    return ldexp(ga, -ea) + ldexp(gb, -eb) + (double)g13[12] * km.d;
+}
+
+template <class Tap, class G>
+__global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ sino, const float *__restrict__ vscale,
+                                                      const ViewGeom *__restrict__ vt,
+                                                      const ViewGeomGrad *__restrict__ vg, EvalConsts ec,
+                                                      float *__restrict__ pair_grad, double *__restrict__ partials,
+                                                      int n_tiles) {
+    __shared__ PairConst<G> lds[kWavesPerBlock][kPairsPerWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int hyp_groups = (ec.B + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t total = (int64_t)n_tiles * hyp_groups;
+    const int64_t w = xcd_work_item(total);
+    if (w >= total) return;  // whole block
+    const int tile = (int)(w / hyp_groups);
+    const int hyp = (int)(w % hyp_groups) * kWavesPerBlock + wave;
+    const bool active = hyp < ec.B;
+    const int64_t p0 = (int64_t)tile * kPairsPerWave;
+    const int np = (int)min((int64_t)kPairsPerWave, (int64_t)ec.n_pairs - p0);
+    const ViewGeom *vth = vt + (int64_t)hyp * ec.n_views;
+
+    int my_a = 0, my_b = 0;
+    if (active && lane < np) {
+        pair_from_index(p0 + lane, ec.n_views, my_a, my_b);
+        PairConst<G> pc;
+        pair_setup<G>(vth[my_a], vth[my_b], ec.R_mm, ec.K, pc);
+        pc.va = my_a;
+        pc.vb = my_b;
+        pc.sa = vscale[my_a];
+        pc.sb = vscale[my_b];
+        lds[wave][lane] = pc;
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const Tap *base = (const Tap *)sino;
+    const float kscale = 2.0f / (float)ec.K;
+    double wave_acc = 0.0;
+    float mine[13];
+    for (int i = 0; i < 13; ++i) mine[i] = 0.0f;
+    for (int q = 0; q < np; ++q) {
+        const PairConst<G> &pc = lds[wave][q];
+        const Tap *sa = base + (int64_t)pc.va * ec.view_elems;
+        const Tap *sb = base + (int64_t)pc.vb * ec.view_elems;
+        // 1. forward sweep
+        float acc = 0.0f;
+        int cnt = 0;
+        for (int k = lane; k < ec.K; k += 64) {
+            G sn, cs;
+            g_sincos(pc.k0 + (G)k * pc.dk, &sn, &cs);
+            bool ha, hb;
+            const float Sa = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, ha);
+            const float Sb = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hb);
+            if (ha && hb) {
+                const float diff = Sa - Sb;
+                acc = fmaf(diff, diff, acc);
+                ++cnt;
+            }
+        }
+        acc = wave_sum(acc);
+        cnt = wave_sum_i(cnt);
+        const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
+        const float den = 1.0f + d * ec.inv_c;
+        const float e = ec.inv_c > 0.0f ? d / den : d;
+        wave_acc += (double)e;
+        float g[13];
+        for (int i = 0; i < 13; ++i) g[i] = 0.0f;
+        if (cnt > 0) {
+            // 2. reverse sweep
+            const float coef = 2.0f / ((float)cnt * den * den);
+            for (int k = lane; k < ec.K; k += 64) {
+                G sn, cs;
+                g_sincos(pc.k0 + (G)k * pc.dk, &sn, &cs);
+                const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
+                const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
+                if (ca.hit && cb.hit) {
+                    const float Sa = sample_at<Tap, G>(ca, sa, ec, pc.inv_f2a, pc.sa);
+                    const float Sb = sample_at<Tap, G>(cb, sb, ec, pc.inv_f2b, pc.sb);
+                    const float gS = coef * (Sa - Sb);
+                    float gk = 0.0f;
+                    lookup_adjoint<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, gS, ca, g, gk);
+                    lookup_adjoint<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, -gS, cb, g + 6, gk);
+                    // kappa_k = kappa_max ((2k + 1) / K - 1)
+                    g[12] = fmaf(gk, (float)(2 * k + 1) * (0.5f * kscale) - 1.0f, g[12]);
+                }
+            }
+            for (int i = 0; i < 13; ++i) g[i] = wave_sum(g[i]);
+        }
+        if (lane == q)
+            for (int i = 0; i < 13; ++i) mine[i] = g[i];
+    }
+    if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
+
+    // 3. per-pair tangent sweeps, one pair per lane
+    if (lane < np) {
+        const int64_t gi = (int64_t)my_a + (int64_t)hyp * ec.n_views;
+        const int64_t gj = (int64_t)my_b + (int64_t)hyp * ec.n_views;
+        float *out = pair_grad + ((int64_t)hyp * ec.n_pairs + p0 + lane) * 12;
+        for (int dir = 0; dir < 12; ++dir)
+            out[dir] = (float)pair_tangent(vth[my_a], vth[my_b], vg[gi], vg[gj], dir, ec.R_mm, mine);
+    }
+}
+
+template <class Tap, class G>
+static hipError_t launch_adj_t(const void *sino, const float *vscale, const ViewGeom *vt, const ViewGeomGrad *vg,
+                               EvalConsts ec, float *pair_grad, double *partials, int n_tiles, hipStream_t s) {
+    const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
+    const int64_t blocks = 8 * ((total + 7) / 8);
+    hipLaunchKernelGGL((ecc_adj_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, sino,
+                       vscale, vt, vg, ec, pair_grad, partials, n_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_ecc_adj(const void *sino, const float *view_scale, const ViewGeom *vt, const ViewGeomGrad *vg,
+                          EvalConsts ec, int dtype, float *pair_grad, double *partials, int n_tiles,
+                          hipStream_t s) {
+    if (ec.geom64) {
+        if (dtype == 0) return launch_adj_t<TapF32, double>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+        if (dtype == 1) return launch_adj_t<TapBF16, double>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+        return launch_adj_t<TapF16, double>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+    }
+    if (dtype == 0) return launch_adj_t<TapF32, float>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+    if (dtype == 1) return launch_adj_t<TapBF16, float>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+    return launch_adj_t<TapF16, float>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+}
+
+// ---------------------------------------------------------------------------
+// grad[b][v][0..5] = sum over partners u (ascending) of the pair (min, max)'s
+// 12-vector: entries 0..5 when v is the first view of the pair, 6..11 else.
+__global__ __launch_bounds__(256) void reduce_grad_kernel(const float *__restrict__ pair_grad, int B, int n_views,
+                                                          float *__restrict__ grad) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * n_views) return;
+    const int b = idx / n_views, v = idx % n_views;
+    const int64_t n_pairs = (int64_t)n_views * (n_views - 1) / 2;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const float *pg = pair_grad + (int64_t)b * n_pairs * 12;
+    for (int u = 0; u < n_views; ++u) {
+        if (u == v) continue;
+        const float *src = u < v ? pg + pair_index(u, v, n_views) * 12 + 6 : pg + pair_index(v, u, n_views) * 12;
+        for (int q = 0; q < 6; ++q) acc[q] += (double)src[q];
+    }
+    for (int q = 0; q < 6; ++q) grad[(int64_t)idx * 6 + q] = (float)acc[q];
+}
+
+hipError_t launch_reduce_grad(const float *pair_grad, int B, int n_views, float *grad, hipStream_t s) {
+    const int n = B * n_views;
+    hipLaunchKernelGGL(reduce_grad_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pair_grad, B, n_views, grad);
+    return hipGetLastError();
+}
+
+}  // namespace ecc

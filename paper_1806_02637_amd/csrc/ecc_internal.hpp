@@ -1,0 +1,98 @@
+// Internal declarations of the ECC engine: data layouts shared by the host
+// engine and the kernels, and the host-side launchers of each kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ecc {
+
+// ---------------------------------------------------------------------------
+// Resident sinogram layout.
+//
+// Row-interleaved: element (view, m, j) holds the pair (S[m][k], S[m+1][k])
+// with k = j - 1, for m = 0..n_alpha-1 and j = 0..n_t+1.  Columns j = 0 and
+// j = n_t + 1 are zero (t beyond the grid reads as 0).  Row m + 1 = n_alpha is
+// the pad row S(pi, t_k) = -S(0, t_{n_t-1-k}).  One 2-element load at
+// (m, k + 1) therefore returns all four bilinear taps of cell (m, k).
+// FP32 storage: 8-byte elements; BF16 / FP16: 4-byte elements.
+// ---------------------------------------------------------------------------
+struct SinoLayout {
+    int32_t n_views, n_alpha, n_t;
+    int32_t row_elems;      // n_t + 2
+    int64_t view_elems;     // n_alpha * row_elems
+    int32_t dtype;          // ECC_F32 / ECC_BF16 / ECC_F16
+    int32_t elem_bytes;     // 8 or 4
+};
+
+inline SinoLayout make_layout(int n_views, int n_alpha, int n_t, int dtype) {
+    SinoLayout L;
+    L.n_views = n_views;
+    L.n_alpha = n_alpha;
+    L.n_t = n_t;
+    L.row_elems = n_t + 2;
+    L.view_elems = (int64_t)n_alpha * L.row_elems;
+    L.dtype = dtype;
+    L.elem_bytes = dtype == 0 ? 8 : 4;
+    return L;
+}
+
+// Per (hypothesis, view) geometry, FP64: moved projection P' = P T(theta)
+// (row-major 3x4), its source, and the view's intrinsics.
+struct ViewGeom {
+    double P[12];
+    double C[3];
+    double f, u0, v0;
+    double pad[2];
+};
+static_assert(sizeof(ViewGeom) == 160, "ViewGeom layout");
+
+// Derivatives of a ViewGeom with respect to the view's 6 motion parameters.
+struct ViewGeomGrad {
+    double dP[6][12];
+    double dC[6][3];
+};
+
+// Scan-wide constants of an evaluation.
+struct EvalConsts {
+    int32_t n_views, n_pairs, K, B;
+    int32_t n_alpha, n_t, row_elems, geom64;
+    int64_t view_elems;
+    double R_mm;
+    float inv_c;       // 1/c, 0 for c = inf
+    float half_w, half_h;
+    float t_max, inv_dt, inv_dalpha;
+    double t_max_d, inv_dt_d, inv_dalpha_d;
+};
+
+// Pair index <-> (a, b), a < b, row-major triangle.
+__host__ __device__ inline int64_t pair_index(int a, int b, int n) {
+    return (int64_t)a * n - (int64_t)a * (a + 1) / 2 + (b - a - 1);
+}
+
+// Launchers (each returns hipError_t of the launch).
+hipError_t launch_sino_weight(const float *images, const double *intr, int n_views, int W, int H, float *gw,
+                              float *gwT, hipStream_t s);
+hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *intr, int n_views, int W, int H,
+                             int n_alpha, int n_t, double ds, double *G, hipStream_t s);
+hipError_t launch_sino_store(const double *G, const float *ext, int n_views, int n_alpha, int n_t, double dt,
+                             int dtype, void *sino, float *view_scale, uint32_t *view_absmax, hipStream_t s);
+hipError_t launch_sino_read(const void *sino, const float *view_scale, SinoLayout L, int view, float *out,
+                            hipStream_t s);
+
+hipError_t launch_view_setup(const double *P, const double *intr, const double *theta, int B, int n_views,
+                             ViewGeom *vt, ViewGeomGrad *vg, hipStream_t s);
+hipError_t launch_ecc_fwd(const void *sino, const float *view_scale, const ViewGeom *vt, EvalConsts ec,
+                          int dtype, float *out_pair, double *partials, int n_tiles, hipStream_t s);
+hipError_t launch_ecc_adj(const void *sino, const float *view_scale, const ViewGeom *vt, const ViewGeomGrad *vg,
+                          EvalConsts ec, int dtype, float *pair_grad, double *partials, int n_tiles,
+                          hipStream_t s);
+hipError_t launch_reduce_cost(const double *partials, int n_tiles, int B, double *out_cost, hipStream_t s);
+hipError_t launch_reduce_grad(const float *pair_grad, int B, int n_views, float *grad, hipStream_t s);
+
+constexpr int kPairsPerWave = 64;
+// zero border (pixels) around the weighted projections read by the line sums
+constexpr int kImgPad = 3;
+constexpr int kWavesPerBlock = 4;
+
+}  // namespace ecc

@@ -1,0 +1,492 @@
+// Host engine behind include/ecc.h: contexts, resident scans under an HBM
+// budget, argument checking, workspace layout and kernel sequencing.  Every
+// entry point returns a status and records a thread-local message; nothing
+// here aborts.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/ecc.h"
+#include "ecc_internal.hpp"
+
+using namespace ecc;
+
+namespace {
+
+thread_local std::string g_err;
+
+ecc_status fail(ecc_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+ecc_status ok() {
+    g_err.clear();
+    return ECC_OK;
+}
+
+#define HIP_TRY(expr)                                                                                       \
+    do {                                                                                                    \
+        hipError_t _e = (expr);                                                                             \
+        if (_e != hipSuccess) return fail(ECC_E_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));        \
+    } while (0)
+
+struct Scan {
+    int32_t n_views = 0, W = 0, H = 0;
+    double *P_dev = nullptr;     // [N][12]
+    double *intr_dev = nullptr;  // [N][3]
+    float *images_dev = nullptr; // [N][H][W] until sinograms exist
+    void *sino_dev = nullptr;
+    float *scale_dev = nullptr;  // [N]
+    uint32_t *absmax_dev = nullptr;
+    SinoLayout layout{};
+    double ds_px = 0.0;
+    bool built = false;
+    uint64_t bytes = 0;
+};
+
+}  // namespace
+
+struct ecc_ctx {
+    int device = 0;
+    uint64_t budget = 0, used = 0;
+    std::mutex mu;
+    std::map<int32_t, Scan *> scans;
+    int32_t next_id = 1;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Allocation charged to the context budget.
+ecc_status ctx_alloc(ecc_ctx *ctx, void **p, uint64_t bytes, uint64_t *charged) {
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(ECC_E_BUDGET, "allocation of %llu bytes exceeds the HBM budget (%llu of %llu in use)",
+                    (unsigned long long)bytes, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) return fail(ECC_E_HIP, "hipMalloc(%llu) failed: %s", (unsigned long long)bytes,
+                                     hipGetErrorString(e));
+    ctx->used += bytes;
+    *charged += bytes;
+    return ECC_OK;
+}
+
+void ctx_free(ecc_ctx *ctx, void *&p, uint64_t bytes, uint64_t *charged) {
+    if (p) {
+        (void)hipFree(p);
+        ctx->used -= bytes;
+        *charged -= bytes;
+        p = nullptr;
+    }
+}
+
+Scan *find_scan(ecc_ctx *ctx, int32_t id) {
+    auto it = ctx->scans.find(id);
+    return it == ctx->scans.end() ? nullptr : it->second;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+int n_tiles_for(int64_t n_pairs) { return (int)((n_pairs + kPairsPerWave - 1) / kPairsPerWave); }
+
+// Workspace layout of an evaluation.
+struct Workspace {
+    uint64_t vt_off, vg_off, part_off, pgrad_off, total;
+};
+
+Workspace workspace_layout(const Scan *s, int B, bool grad) {
+    const int64_t n_pairs = (int64_t)s->n_views * (s->n_views - 1) / 2;
+    Workspace w{};
+    uint64_t off = 0;
+    w.vt_off = off;
+    off += align256(sizeof(ViewGeom) * (uint64_t)B * s->n_views);
+    w.vg_off = off;
+    if (grad) off += align256(sizeof(ViewGeomGrad) * (uint64_t)B * s->n_views);
+    w.part_off = off;
+    off += align256(sizeof(double) * (uint64_t)B * n_tiles_for(n_pairs));
+    w.pgrad_off = off;
+    if (grad) off += align256(sizeof(float) * 12ull * (uint64_t)B * n_pairs);
+    w.total = off;
+    return w;
+}
+
+ecc_status free_scan_memory(ecc_ctx *ctx, Scan *s) {
+    (void)hipDeviceSynchronize();
+    ctx_free(ctx, (void *&)s->P_dev, sizeof(double) * 12ull * s->n_views, &s->bytes);
+    ctx_free(ctx, (void *&)s->intr_dev, sizeof(double) * 3ull * s->n_views, &s->bytes);
+    ctx_free(ctx, (void *&)s->images_dev, sizeof(float) * (uint64_t)s->n_views * s->W * s->H, &s->bytes);
+    if (s->sino_dev)
+        ctx_free(ctx, s->sino_dev, (uint64_t)s->layout.elem_bytes * s->layout.view_elems * s->n_views, &s->bytes);
+    ctx_free(ctx, (void *&)s->scale_dev, sizeof(float) * s->n_views, &s->bytes);
+    ctx_free(ctx, (void *&)s->absmax_dev, sizeof(uint32_t) * s->n_views, &s->bytes);
+    return ECC_OK;
+}
+
+ecc_status check_eval(ecc_ctx *ctx, int32_t scan_id, int32_t B, const ecc_eval_params *prm, Scan **out) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    if (!s->built) return fail(ECC_E_STATE, "scan %d has no sinograms yet", scan_id);
+    if (B < 1 || B > 65536) return fail(ECC_E_ARG, "B = %d out of range [1, 65536]", B);
+    if (!prm) return fail(ECC_E_ARG, "null params");
+    if (prm->K < 1 || prm->K > 4096) return fail(ECC_E_ARG, "K = %d out of range [1, 4096]", prm->K);
+    if (!(prm->R_mm > 0.0) || !isfinite(prm->R_mm)) return fail(ECC_E_ARG, "R_mm must be positive and finite");
+    if (prm->geom != ECC_GEOM_F32 && prm->geom != ECC_GEOM_F64) return fail(ECC_E_ARG, "unknown geom %d", prm->geom);
+    if (isnan(prm->c)) return fail(ECC_E_ARG, "c is NaN");
+    *out = s;
+    return ECC_OK;
+}
+
+EvalConsts make_consts(const Scan *s, int B, const ecc_eval_params *prm) {
+    EvalConsts ec{};
+    ec.n_views = s->n_views;
+    ec.n_pairs = (int32_t)((int64_t)s->n_views * (s->n_views - 1) / 2);
+    ec.K = prm->K;
+    ec.B = B;
+    ec.n_alpha = s->layout.n_alpha;
+    ec.n_t = s->layout.n_t;
+    ec.row_elems = s->layout.row_elems;
+    ec.view_elems = s->layout.view_elems;
+    ec.geom64 = prm->geom == ECC_GEOM_F64;
+    ec.R_mm = prm->R_mm;
+    ec.inv_c = (prm->c > 0.0 && isfinite(prm->c)) ? (float)(1.0 / prm->c) : 0.0f;
+    ec.half_w = 0.5f * s->W;
+    ec.half_h = 0.5f * s->H;
+    const double t_max = 0.5 * sqrt((double)s->W * s->W + (double)s->H * s->H);
+    const double dt = 2.0 * t_max / (s->layout.n_t - 1);
+    const double dalpha = M_PI / s->layout.n_alpha;
+    ec.t_max_d = t_max;
+    ec.inv_dt_d = 1.0 / dt;
+    ec.inv_dalpha_d = 1.0 / dalpha;
+    ec.t_max = (float)t_max;
+    ec.inv_dt = (float)(1.0 / dt);
+    ec.inv_dalpha = (float)(1.0 / dalpha);
+    return ec;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ecc_last_error(void) { return g_err.c_str(); }
+
+ecc_status ecc_create(ecc_ctx **out, int hip_device, uint64_t hbm_budget_bytes) {
+    if (!out) return fail(ECC_E_ARG, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(ECC_E_HIP, "hipGetDeviceCount failed: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= n) return fail(ECC_E_ARG, "device %d not present (%d devices)", hip_device, n);
+    ecc_ctx *ctx = new ecc_ctx();
+    ctx->device = hip_device;
+    ctx->budget = hbm_budget_bytes;
+    *out = ctx;
+    return ok();
+}
+
+ecc_status ecc_destroy(ecc_ctx *ctx) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    {
+        DeviceGuard g(ctx->device);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto &kv : ctx->scans) {
+            free_scan_memory(ctx, kv.second);
+            delete kv.second;
+        }
+        ctx->scans.clear();
+    }
+    delete ctx;
+    return ok();
+}
+
+ecc_status ecc_scan_load(ecc_ctx *ctx, int32_t *scan_id, int32_t n_views, int32_t W, int32_t H, const double *P,
+                         const double *intr, const float *images, int32_t images_on_device) {
+    if (!ctx || !scan_id || !P || !intr || !images) return fail(ECC_E_ARG, "null argument");
+    if (n_views < 2 || n_views > 65536) return fail(ECC_E_ARG, "n_views = %d out of range [2, 65536]", n_views);
+    if (W < 2 || H < 2 || W > 32768 || H > 32768) return fail(ECC_E_ARG, "detector %dx%d out of range", W, H);
+    int sign = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const double *p = P + 12 * v;
+        for (int i = 0; i < 12; ++i)
+            if (!isfinite(p[i])) return fail(ECC_E_ARG, "non-finite projection matrix entry (view %d)", v);
+        for (int i = 0; i < 3; ++i)
+            if (!isfinite(intr[3 * v + i])) return fail(ECC_E_ARG, "non-finite intrinsics (view %d)", v);
+        if (!(intr[3 * v] > 0.0)) return fail(ECC_E_ARG, "focal length must be positive (view %d)", v);
+        const double det = p[0] * (p[5] * p[10] - p[6] * p[9]) - p[1] * (p[4] * p[10] - p[6] * p[8]) +
+                           p[2] * (p[4] * p[9] - p[5] * p[8]);
+        const int sg = det > 0 ? 1 : (det < 0 ? -1 : 0);
+        if (sg == 0) return fail(ECC_E_ARG, "singular left 3x3 of P (view %d)", v);
+        if (sign == 0) sign = sg;
+        if (sg != sign) return fail(ECC_E_ARG, "views differ in detector handedness (sign of det M, view %d)", v);
+    }
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = new Scan();
+    s->n_views = n_views;
+    s->W = W;
+    s->H = H;
+    ecc_status st;
+    const uint64_t img_bytes = sizeof(float) * (uint64_t)n_views * W * H;
+    if ((st = ctx_alloc(ctx, (void **)&s->P_dev, sizeof(double) * 12ull * n_views, &s->bytes)) ||
+        (st = ctx_alloc(ctx, (void **)&s->intr_dev, sizeof(double) * 3ull * n_views, &s->bytes)) ||
+        (st = ctx_alloc(ctx, (void **)&s->images_dev, img_bytes, &s->bytes)) ||
+        (st = ctx_alloc(ctx, (void **)&s->scale_dev, sizeof(float) * n_views, &s->bytes)) ||
+        (st = ctx_alloc(ctx, (void **)&s->absmax_dev, sizeof(uint32_t) * n_views, &s->bytes))) {
+        std::string msg = g_err;
+        free_scan_memory(ctx, s);
+        delete s;
+        g_err = msg;
+        return st;
+    }
+    hipError_t e1 = hipMemcpy(s->P_dev, P, sizeof(double) * 12ull * n_views, hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(s->intr_dev, intr, sizeof(double) * 3ull * n_views, hipMemcpyHostToDevice);
+    hipError_t e3 = hipMemcpy(s->images_dev, images, img_bytes,
+                              images_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        hipError_t e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+        free_scan_memory(ctx, s);
+        delete s;
+        return fail(ECC_E_HIP, "copying scan inputs failed: %s", hipGetErrorString(e));
+    }
+    const int32_t id = ctx->next_id++;
+    ctx->scans[id] = s;
+    *scan_id = id;
+    return ok();
+}
+
+static ecc_status install_sinograms(ecc_ctx *ctx, Scan *s, int32_t n_alpha, int32_t n_t, double ds_px, int32_t dtype,
+                                    const float *ext_host, const float *ext_dev, hipStream_t stream) {
+    const SinoLayout L = make_layout(s->n_views, n_alpha, n_t, dtype);
+    const uint64_t sino_bytes = (uint64_t)L.elem_bytes * L.view_elems * s->n_views;
+    ecc_status st = ctx_alloc(ctx, &s->sino_dev, sino_bytes, &s->bytes);
+    if (st) return st;
+    s->layout = L;
+    // temporaries (charged while they live)
+    uint64_t tmp_charged = 0;
+    float *gw = nullptr, *gwT = nullptr, *ext_tmp = nullptr;
+    double *G = nullptr;
+    const uint64_t pad_bytes = sizeof(float) * (uint64_t)s->n_views * (s->W + 2 * kImgPad) * (s->H + 2 * kImgPad);
+    const uint64_t G_bytes = sizeof(double) * (uint64_t)s->n_views * n_alpha * n_t;
+    const uint64_t ext_bytes = sizeof(float) * (uint64_t)s->n_views * (n_alpha + 1) * n_t;
+    auto cleanup = [&]() {
+        ctx_free(ctx, (void *&)gw, pad_bytes, &tmp_charged);
+        ctx_free(ctx, (void *&)gwT, pad_bytes, &tmp_charged);
+        ctx_free(ctx, (void *&)G, G_bytes, &tmp_charged);
+        ctx_free(ctx, (void *&)ext_tmp, ext_bytes, &tmp_charged);
+    };
+    auto bail = [&](ecc_status code) {
+        std::string msg = g_err;
+        (void)hipStreamSynchronize(stream);
+        cleanup();
+        ctx_free(ctx, s->sino_dev, sino_bytes, &s->bytes);
+        g_err = msg;
+        return code;
+    };
+    hipError_t e;
+    const float *ext = ext_dev;
+    if (ext_host) {
+        if ((st = ctx_alloc(ctx, (void **)&ext_tmp, ext_bytes, &tmp_charged))) return bail(st);
+        if ((e = hipMemcpyAsync(ext_tmp, ext_host, ext_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return bail(fail(ECC_E_HIP, "sinogram upload failed: %s", hipGetErrorString(e)));
+        ext = ext_tmp;
+    }
+    if (!ext) {
+        if ((st = ctx_alloc(ctx, (void **)&gw, pad_bytes, &tmp_charged)) ||
+            (st = ctx_alloc(ctx, (void **)&gwT, pad_bytes, &tmp_charged)) ||
+            (st = ctx_alloc(ctx, (void **)&G, G_bytes, &tmp_charged)))
+            return bail(st);
+        if ((e = hipMemsetAsync(gw, 0, pad_bytes, stream)) != hipSuccess ||
+            (e = hipMemsetAsync(gwT, 0, pad_bytes, stream)) != hipSuccess ||
+            (e = launch_sino_weight(s->images_dev, s->intr_dev, s->n_views, s->W, s->H, gw, gwT, stream)) !=
+                hipSuccess ||
+            (e = launch_sino_radon(gw, gwT, s->intr_dev, s->n_views, s->W, s->H, n_alpha, n_t, ds_px, G, stream)) !=
+                hipSuccess)
+            return bail(fail(ECC_E_HIP, "sinogram build launch failed: %s", hipGetErrorString(e)));
+    }
+    const double t_max = 0.5 * sqrt((double)s->W * s->W + (double)s->H * s->H);
+    const double dt = 2.0 * t_max / (n_t - 1);
+    if ((e = launch_sino_store(G, ext, s->n_views, n_alpha, n_t, dt, dtype, s->sino_dev, s->scale_dev,
+                               s->absmax_dev, stream)) != hipSuccess)
+        return bail(fail(ECC_E_HIP, "sinogram store launch failed: %s", hipGetErrorString(e)));
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess)
+        return bail(fail(ECC_E_HIP, "sinogram build failed: %s", hipGetErrorString(e)));
+    cleanup();
+    ctx_free(ctx, (void *&)s->images_dev, sizeof(float) * (uint64_t)s->n_views * s->W * s->H, &s->bytes);
+    s->ds_px = ds_px;
+    s->built = true;
+    return ok();
+}
+
+ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, double ds_px,
+                                    int32_t dtype, void *stream) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536)
+        return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
+    if (!(ds_px > 0.0) || ds_px > 1.0) return fail(ECC_E_ARG, "ds_px must be in (0, 1]");
+    if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    if (s->built || !s->images_dev) return fail(ECC_E_STATE, "scan %d already has sinograms", scan_id);
+    return install_sinograms(ctx, s, n_alpha, n_t, ds_px, dtype, nullptr, nullptr, (hipStream_t)stream);
+}
+
+ecc_status ecc_scan_set_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, const float *sino,
+                                  int32_t sino_on_device, int32_t dtype) {
+    if (!ctx || !sino) return fail(ECC_E_ARG, "null argument");
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536)
+        return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
+    if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    if (s->built) return fail(ECC_E_STATE, "scan %d already has sinograms", scan_id);
+    return install_sinograms(ctx, s, n_alpha, n_t, 0.0, dtype, sino_on_device ? nullptr : sino,
+                             sino_on_device ? sino : nullptr, nullptr);
+}
+
+ecc_status ecc_scan_read_sinogram(ecc_ctx *ctx, int32_t scan_id, int32_t view, float *out) {
+    if (!ctx || !out) return fail(ECC_E_ARG, "null argument");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    if (!s->built) return fail(ECC_E_STATE, "scan %d has no sinograms yet", scan_id);
+    if (view < 0 || view >= s->n_views) return fail(ECC_E_ARG, "view %d out of range", view);
+    const uint64_t n = (uint64_t)(s->layout.n_alpha + 1) * s->layout.n_t;
+    float *tmp = nullptr;
+    HIP_TRY(hipMalloc((void **)&tmp, n * sizeof(float)));
+    hipError_t e = launch_sino_read(s->sino_dev, s->scale_dev, s->layout, view, tmp, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, tmp, n * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(ECC_E_HIP, "reading sinogram failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+ecc_status ecc_scan_free(ecc_ctx *ctx, int32_t scan_id) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    DeviceGuard g(ctx->device);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    free_scan_memory(ctx, s);
+    ctx->scans.erase(scan_id);
+    delete s;
+    return ok();
+}
+
+ecc_status ecc_scan_bytes(ecc_ctx *ctx, int32_t scan_id, uint64_t *bytes) {
+    if (!ctx || !bytes) return fail(ECC_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    *bytes = s->bytes;
+    return ok();
+}
+
+ecc_status ecc_scan_info(ecc_ctx *ctx, int32_t scan_id, int32_t *n_views, int32_t *n_pairs, int32_t *n_alpha,
+                         int32_t *n_t, int32_t *dtype) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    if (n_views) *n_views = s->n_views;
+    if (n_pairs) *n_pairs = (int32_t)((int64_t)s->n_views * (s->n_views - 1) / 2);
+    if (n_alpha) *n_alpha = s->layout.n_alpha;
+    if (n_t) *n_t = s->layout.n_t;
+    if (dtype) *dtype = s->built ? s->layout.dtype : -1;
+    return ok();
+}
+
+ecc_status ecc_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, int32_t B, int32_t with_grad, uint64_t *bytes) {
+    if (!ctx || !bytes) return fail(ECC_E_ARG, "null argument");
+    if (B < 1 || B > 65536) return fail(ECC_E_ARG, "B = %d out of range [1, 65536]", B);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    *bytes = workspace_layout(s, B, with_grad != 0).total;
+    return ok();
+}
+
+ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev, const ecc_eval_params *params,
+                    double *out_cost_dev, float *out_pair_dev, void *workspace_dev, uint64_t workspace_bytes,
+                    void *stream) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    // the lock spans the (asynchronous) launches so that a concurrent
+    // ecc_scan_free cannot release the scan between check and launch
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = nullptr;
+    ecc_status st;
+    if ((st = check_eval(ctx, scan_id, B, params, &s))) return st;
+    if (!theta_dev || !out_cost_dev || !workspace_dev) return fail(ECC_E_ARG, "null device pointer");
+    const Workspace w = workspace_layout(s, B, false);
+    if (workspace_bytes < w.total)
+        return fail(ECC_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
+                    (unsigned long long)workspace_bytes, (unsigned long long)w.total);
+    DeviceGuard g(ctx->device);
+    hipStream_t hs = (hipStream_t)stream;
+    char *ws = (char *)workspace_dev;
+    ViewGeom *vt = (ViewGeom *)(ws + w.vt_off);
+    double *partials = (double *)(ws + w.part_off);
+    const EvalConsts ec = make_consts(s, B, params);
+    const int n_tiles = n_tiles_for(ec.n_pairs);
+    HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, nullptr, hs));
+    HIP_TRY(launch_ecc_fwd(s->sino_dev, s->scale_dev, vt, ec, s->layout.dtype, out_pair_dev, partials, n_tiles, hs));
+    HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
+    return ok();
+}
+
+ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                         const ecc_eval_params *params, double *out_cost_dev, float *grad_dev,
+                         float *out_pair_grad_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = nullptr;
+    ecc_status st;
+    if ((st = check_eval(ctx, scan_id, B, params, &s))) return st;
+    if (!theta_dev || !out_cost_dev || !grad_dev || !workspace_dev) return fail(ECC_E_ARG, "null device pointer");
+    const Workspace w = workspace_layout(s, B, true);
+    if (workspace_bytes < w.total)
+        return fail(ECC_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
+                    (unsigned long long)workspace_bytes, (unsigned long long)w.total);
+    DeviceGuard g(ctx->device);
+    hipStream_t hs = (hipStream_t)stream;
+    char *ws = (char *)workspace_dev;
+    ViewGeom *vt = (ViewGeom *)(ws + w.vt_off);
+    ViewGeomGrad *vg = (ViewGeomGrad *)(ws + w.vg_off);
+    double *partials = (double *)(ws + w.part_off);
+    float *pgrad = out_pair_grad_dev ? out_pair_grad_dev : (float *)(ws + w.pgrad_off);
+    const EvalConsts ec = make_consts(s, B, params);
+    const int n_tiles = n_tiles_for(ec.n_pairs);
+    HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, vg, hs));
+    HIP_TRY(launch_ecc_adj(s->sino_dev, s->scale_dev, vt, vg, ec, s->layout.dtype, pgrad, partials, n_tiles, hs));
+    HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
+    HIP_TRY(launch_reduce_grad(pgrad, B, s->n_views, grad_dev, hs));
+    return ok();
+}
+
+}  // extern "C"

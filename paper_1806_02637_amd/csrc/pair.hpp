@@ -1,0 +1,72 @@
+// Per-pair device helpers shared by the forward and adjoint kernels: pair
+// indexing, the FP64 per-pair geometry, wave reductions and the XCD-aware
+// block numbering.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ecc_internal.hpp"
+#include "lookup.hpp"
+#include "projective.hpp"
+
+namespace ecc {
+
+// Pair (a, b) from its row-major triangle index.
+__device__ __forceinline__ void pair_from_index(int64_t p, int n, int &a, int &b) {
+    const double m = 2.0 * n - 1.0;
+    int aa = (int)floor(0.5 * (m - sqrt(m * m - 8.0 * (double)p)));
+    if (aa < 0) aa = 0;
+    if (aa > n - 2) aa = n - 2;
+    while (aa > 0 && pair_index(aa, aa + 1, n) > p) --aa;
+    while (aa < n - 2 && pair_index(aa + 1, aa + 2, n) <= p) ++aa;
+    a = aa;
+    b = (int)(p - pair_index(aa, aa + 1, n)) + aa + 1;
+}
+
+// FP64 per-pair geometry -> the per-plane constants of one pair.
+template <class G>
+__device__ __forceinline__ void pair_setup(const ViewGeom &A, const ViewGeom &Bv, double R_mm, int K,
+                                           PairConst<G> &pc) {
+    double u1[3], u2[3], km;
+    pencil(A.C, Bv.C, R_mm, u1, u2, km);
+    double Ha[6], Hb[6];
+    line_map(A.P, A.C, u1, u2, A.u0, A.v0, Ha);
+    line_map(Bv.P, A.C, u1, u2, Bv.u0, Bv.v0, Hb);
+    // (alpha, t) of a line do not change under a positive scale: bring both
+    // maps to unit magnitude with an exact power of two
+    double ma = 0.0, mb = 0.0;
+    for (int i = 0; i < 6; ++i) {
+        ma = fmax(ma, fabs(Ha[i]));
+        mb = fmax(mb, fabs(Hb[i]));
+    }
+    const int ea = ma > 0.0 ? ilogb(ma) : 0, eb = mb > 0.0 ? ilogb(mb) : 0;
+    for (int i = 0; i < 6; ++i) {
+        pc.ha[i] = (G)ldexp(Ha[i], -ea);
+        pc.hb[i] = (G)ldexp(Hb[i], -eb);
+    }
+    const double dk = 2.0 * km / K;
+    pc.k0 = (G)(-km + 0.5 * dk);
+    pc.dk = (G)dk;
+    pc.inv_f2a = (float)(1.0 / (A.f * A.f));
+    pc.inv_f2b = (float)(1.0 / (Bv.f * Bv.f));
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+__device__ __forceinline__ int wave_sum_i(int x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Logical work item of a block under the XCD-aware numbering.
+__device__ __forceinline__ int64_t xcd_work_item(int64_t total) {
+    const int64_t per = (total + 7) / 8;
+    const int64_t i = blockIdx.x;
+    return (i % 8) * per + i / 8;
+}
+
+}  // namespace ecc

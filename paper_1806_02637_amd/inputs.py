@@ -158,10 +158,11 @@ def sphere_phantom(radius_mm: float, density: float = 1.0) -> Phantom:
 
 
 def project(geom: ScanGeometry, phantom: Phantom, views=None, device: str = "cpu",
-            chunk_rows: int | None = None) -> np.ndarray:
+            chunk_rows: int | None = None, as_tensor: bool = False):
     """Analytic line integrals through every pixel centre, FP64, returned FP32.
 
-    Returns images [n_sel, H, W] (row v, column u).  ``device`` selects where
+    Returns images [n_sel, H, W] (row v, column u) as a NumPy array, or as an
+    FP32 torch tensor on ``device`` with ``as_tensor``.  ``device`` selects where
     torch evaluates the intersections ("cpu" or "cuda"); the arithmetic is
     FP64 either way.  For ray X = C + tau * omega (|omega| = 1) and an ellipsoid
     (x_e, a_e, Q_e): y = diag(1/a) Q^T (C - x_e), w = diag(1/a) Q^T omega,
@@ -176,7 +177,8 @@ def project(geom: ScanGeometry, phantom: Phantom, views=None, device: str = "cpu
     dev = torch.device(device)
     f, u0, v0 = geom.f_px, geom.u0, geom.v0
     W, H = geom.W, geom.H
-    out = np.empty((len(views), H, W), dtype=np.float32)
+    out = torch.empty((len(views), H, W), dtype=torch.float32, device=dev) if as_tensor else \
+        np.empty((len(views), H, W), dtype=np.float32)
     cen = torch.as_tensor(phantom.centers, dtype=torch.float64, device=dev)
     inv_a = torch.as_tensor(1.0 / phantom.semi_axes, dtype=torch.float64, device=dev)
     QT = torch.as_tensor(np.transpose(phantom.axes, (0, 2, 1)).copy(), dtype=torch.float64, device=dev)
@@ -209,7 +211,10 @@ def project(geom: ScanGeometry, phantom: Phantom, views=None, device: str = "cpu
                 acc += rho[e] * torch.where(D > 0, 2.0 * torch.sqrt(D.clamp_min(0.0)) / ww,
                                             torch.zeros_like(D))
             img[r0:r1] = acc
-        out[oi] = img.to(torch.float32).cpu().numpy()
+        if as_tensor:
+            out[oi] = img.to(torch.float32)
+        else:
+            out[oi] = img.to(torch.float32).cpu().numpy()
     return out
 
 
