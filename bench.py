@@ -80,6 +80,99 @@ def cpu_baseline(w, imgs_dev, P, intr, thetas, budget_s=20.0, seed=5):
                       f"({evals} evals in {dt:.1f} s; sinogram cells filled beforehand in {fill:.1f} s)"}
 
 
+def timed(fn, steps, warmup):
+    """Mean ms per call of fn() on the current stream (HIP events)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps):
+    """Precision forms and the adjoint on the same workload, each against the
+    plain FP32 step (same GPU, same inputs)."""
+    evals = w.B * w.n_pairs * w.K
+    out = {}
+    for dtype in ("bf16", "f16"):
+        sc = eng.load_scan(P, intr, imgs)
+        sc.build_sinograms(w.n_alpha, w.n_t, w.ds_px, dtype)
+        ws = sc.workspace(w.B, False)
+        ms = timed(lambda: sc.cost(th_dev, w.K, w.R_mm, workspace=ws), steps, 2)
+        out[dtype] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3), "roofline_frac_hbm": 16 * evals / (ms * 1e-3) / 8e12}
+        sc.free()
+    ws = scan32.workspace(w.B, False)
+    ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, geom="f64", workspace=ws), steps, 2)
+    out["f32_geom64"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3)}
+    wsg = scan32.workspace(w.B, True)
+    ms = timed(lambda: scan32.cost_grad(th_dev, w.K, w.R_mm, workspace=wsg), max(3, steps // 2), 1)
+    out["adjoint_f32"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
+                          "note": "cost + gradient w.r.t. all B x N x 6 motion parameters"}
+    return out
+
+
+def measure_serving(eng, n_requests=48, seed=7, load=0.8):
+    """Served form: 8 resident scans of uneven view counts, Poisson arrivals of
+    64-hypothesis requests (half cost+gradient).  The same trace is served (a)
+    with BF16 sinograms by the continuous-batching server (4 slots) and (b)
+    serially with plain FP32 sinograms (1 slot); the arrival rate is `load`
+    times the serial FP32 capacity."""
+    import torch
+
+    from paper_1806_02637_amd import inputs
+    from paper_1806_02637_amd.serve import Server, latency_summary, poisson_arrivals, replay
+
+    wls = inputs.serve_workloads()
+    scans = {"bf16": [], "f32": []}
+    for wl in wls:
+        g = wl.geom
+        imgs = inputs.project(g, wl.phantom(), device="cuda", as_tensor=True)
+        for dt in ("bf16", "f32"):
+            sc = eng.load_scan(g.projection_matrices(), g.intrinsics(), imgs)
+            sc.build_sinograms(wl.n_alpha, wl.n_t, wl.ds_px, dt)
+            scans[dt].append(sc)
+        del imgs
+        torch.cuda.empty_cache()
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_requests):
+        j = int(rng.integers(len(wls)))
+        wl = wls[j]
+        reqs.append((j, inputs.random_motion(int(rng.integers(1 << 30)), wl.B, wl.geom.n_views), bool(i % 2)))
+    evals = sum(wls[j].B * wls[j].n_pairs * wls[j].K for j, _, _ in reqs)
+
+    def trace(kind, arrivals):
+        return [(float(arrivals[i]), scans[kind][j], th, wls[j].K, wls[j].R_mm, g)
+                for i, (j, th, g) in enumerate(reqs)]
+
+    # serial FP32 capacity: back-to-back arrivals on one slot
+    srv = Server(eng, n_slots=1, arena_bytes=4 << 30)
+    _, busy = replay(srv, trace("f32", np.zeros(n_requests)))
+    srv.close()
+    rate = load * n_requests / busy
+    arrivals = poisson_arrivals(rate, n_requests, seed)
+    out = {"requests": n_requests, "arrival_rate_per_s": rate, "load_vs_serial_f32_capacity": load,
+           "scans_views": [wl.geom.n_views for wl in wls], "hypotheses_per_request": 64, "grad_fraction": 0.5}
+    for name, kind, slots in (("served_bf16", "bf16", 4), ("serial_f32", "f32", 1)):
+        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30)
+        res, makespan = replay(srv, trace(kind, arrivals))
+        srv.close()
+        lat = latency_summary(res)
+        out[name] = {"p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"], "mean_ms": lat["mean_ms"],
+                     "makespan_s": makespan, "evals_per_s": evals / makespan, "slots": slots}
+    for lst in scans.values():
+        for sc in lst:
+            sc.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,7 +182,11 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--geom", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ecc_fwd_full496_traffic.json"))
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device 5 times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the engine has no multi-GPU path",
@@ -99,6 +196,16 @@ def main():
     import torch
 
     from paper_1806_02637_amd import engine, inputs
+
+    if args.copy_probe:
+        n = 1 << 28  # 2^28 floats = 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 5}))
+        return
 
     w = inputs.WORKLOADS[args.workload]
     g = w.geom
@@ -172,9 +279,17 @@ def main():
         "sino_build": {"ms": build_ms, "cells_per_s": cells / (build_ms * 1e-3),
                        "line_samples_per_s_upper": cells * n_s / (build_ms * 1e-3)},
     }
+    if not args.no_variants:
+        _log("precision forms and adjoint")
+        rec["variants"] = measure_variants(eng, w, P, intr, imgs, scan, th_dev, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
         _log("timing the FP64 oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(w, imgs, P, intr, thetas)
+    if not args.no_serve:
+        del imgs
+        torch.cuda.empty_cache()
+        _log("served form")
+        rec["serve"] = measure_serving(eng)
     print(json.dumps(rec), flush=True)
     eng.close()
 

@@ -157,6 +157,56 @@ ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double 
 ecc_status ecc_scan_info(ecc_ctx *ctx, int32_t scan_id, int32_t *n_views, int32_t *n_pairs, int32_t *n_alpha,
                          int32_t *n_t, int32_t *dtype);
 
+
+/* ---------------------------------------------------------------------------
+ * Served form: continuous batching of evaluation requests over resident
+ * scans.  A server owns `n_slots` HIP streams and one device arena of
+ * `arena_bytes` (the HBM budget for requests' workspaces and buffers) plus a
+ * pinned host staging arena.  A worker thread admits queued requests in
+ * arrival order as soon as a slot is free and the request's device bytes fit
+ * in the arena; admitted requests run concurrently on their slots' streams
+ * while later ones keep arriving.  Each request's kernels and reductions do
+ * not depend on its neighbours, so its result is the same alone and in the
+ * mix (bitwise).  A request for a scan freed before admission fails with
+ * ECC_E_NOSCAN; one larger than the whole arena fails with ECC_E_BUDGET.
+ * ------------------------------------------------------------------------- */
+typedef struct ecc_server ecc_server;
+
+typedef struct {
+    double queue_ms;  /* submit -> admission */
+    double run_ms;    /* admission -> results on the host */
+    double total_ms;  /* submit -> results on the host (the request latency) */
+    int32_t slot;     /* stream slot the request ran on */
+    int32_t status;   /* ecc_status of the request */
+} ecc_request_stats;
+
+/* Creates a server on ctx.  n_slots in [1, 16]; arena_bytes > 0. */
+ecc_status ecc_server_create(ecc_ctx *ctx, ecc_server **out, int32_t n_slots, uint64_t arena_bytes);
+
+/* Queues a request: B hypotheses theta_host [B][n_views][6] FP64 (host memory,
+ * copied), evaluation parameters, cost only (with_grad = 0) or cost and
+ * gradient.  Returns its id.  Never blocks on the device. */
+ecc_status ecc_server_submit(ecc_server *srv, int32_t scan_id, int32_t B, const double *theta_host,
+                             const ecc_eval_params *params, int32_t with_grad, int64_t *request_id);
+
+/* Sets *done to 1 once the request has finished (successfully or not). */
+ecc_status ecc_server_poll(ecc_server *srv, int64_t request_id, int32_t *done);
+
+/* Waits for a request, copies its results -- cost_host [B] FP64 and, for
+ * gradient requests, grad_host [B][n_views][6] FP32 (may be NULL) -- and its
+ * timing into stats (may be NULL), then forgets the request.  Returns the
+ * request's own status. */
+ecc_status ecc_server_wait(ecc_server *srv, int64_t request_id, double *cost_host, float *grad_host,
+                           ecc_request_stats *stats);
+
+/* Device bytes a request occupies in the arena while it runs. */
+ecc_status ecc_server_request_bytes(ecc_server *srv, int32_t scan_id, int32_t B, int32_t with_grad,
+                                    uint64_t *bytes);
+
+/* Stops the worker after the requests already admitted finish, fails the
+ * queued ones, and frees the server's streams and arenas. */
+ecc_status ecc_server_destroy(ecc_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

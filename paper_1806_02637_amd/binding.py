@@ -23,7 +23,8 @@ DTYPES = {"f32": ECC_F32, "bf16": ECC_BF16, "f16": ECC_F16}
 SYMBOLS = (
     "ecc_last_error", "ecc_create", "ecc_destroy", "ecc_scan_load", "ecc_scan_build_sinograms",
     "ecc_scan_set_sinograms", "ecc_scan_read_sinogram", "ecc_scan_free", "ecc_scan_bytes", "ecc_workspace_bytes",
-    "ecc_cost", "ecc_cost_grad", "ecc_scan_info",
+    "ecc_cost", "ecc_cost_grad", "ecc_scan_info", "ecc_server_create", "ecc_server_submit", "ecc_server_poll",
+    "ecc_server_wait", "ecc_server_request_bytes", "ecc_server_destroy",
 )
 
 
@@ -35,6 +36,11 @@ class EccError(RuntimeError):
 
 class EvalParams(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("geom", ctypes.c_int32), ("R_mm", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("slot", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
 _lib = None
@@ -56,6 +62,13 @@ _SIGNATURES = {
     "ecc_cost": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _U64, _P], _I32),
     "ecc_cost_grad": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _P, _U64, _P], _I32),
     "ecc_scan_info": ([_P, _I32] + [ctypes.POINTER(_I32)] * 5, _I32),
+    "ecc_server_create": ([_P, ctypes.POINTER(_P), _I32, _U64], _I32),
+    "ecc_server_submit": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _I32, ctypes.POINTER(ctypes.c_int64)],
+                          _I32),
+    "ecc_server_poll": ([_P, ctypes.c_int64, ctypes.POINTER(_I32)], _I32),
+    "ecc_server_wait": ([_P, ctypes.c_int64, _P, _P, ctypes.POINTER(RequestStats)], _I32),
+    "ecc_server_request_bytes": ([_P, _I32, _I32, _I32, ctypes.POINTER(_U64)], _I32),
+    "ecc_server_destroy": ([_P], _I32),
 }
 
 
@@ -150,3 +163,41 @@ def ecc_scan_info(ctx: int, scan_id: int):
     vals = [_I32() for _ in range(5)]
     _check(load_library().ecc_scan_info(ctx, scan_id, *[ctypes.byref(v) for v in vals]), "ecc_scan_info")
     return tuple(v.value for v in vals)
+
+
+def ecc_server_create(ctx: int, n_slots: int, arena_bytes: int) -> int:
+    out = _P()
+    _check(load_library().ecc_server_create(ctx, ctypes.byref(out), n_slots, arena_bytes), "ecc_server_create")
+    return out.value
+
+
+def ecc_server_submit(srv: int, scan_id: int, B: int, theta_host_ptr: int, params: EvalParams,
+                      with_grad: int) -> int:
+    rid = ctypes.c_int64()
+    _check(load_library().ecc_server_submit(srv, scan_id, B, theta_host_ptr, ctypes.byref(params), with_grad,
+                                            ctypes.byref(rid)), "ecc_server_submit")
+    return rid.value
+
+
+def ecc_server_poll(srv: int, request_id: int) -> bool:
+    done = _I32()
+    _check(load_library().ecc_server_poll(srv, request_id, ctypes.byref(done)), "ecc_server_poll")
+    return bool(done.value)
+
+
+def ecc_server_wait(srv: int, request_id: int, cost_host_ptr: int, grad_host_ptr: int) -> RequestStats:
+    st = RequestStats()
+    _check(load_library().ecc_server_wait(srv, request_id, cost_host_ptr, grad_host_ptr, ctypes.byref(st)),
+           "ecc_server_wait")
+    return st
+
+
+def ecc_server_request_bytes(srv: int, scan_id: int, B: int, with_grad: int) -> int:
+    out = _U64()
+    _check(load_library().ecc_server_request_bytes(srv, scan_id, B, with_grad, ctypes.byref(out)),
+           "ecc_server_request_bytes")
+    return out.value
+
+
+def ecc_server_destroy(srv: int):
+    _check(load_library().ecc_server_destroy(srv), "ecc_server_destroy")

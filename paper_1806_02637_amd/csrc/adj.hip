@@ -33,20 +33,21 @@ template <class Tap, class G>
 __device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const Tap *sview, const EvalConsts &ec,
                                                float inv_f2, float scale, float gS, const LineCoord<G> &c,
                                                float gH[6], float &gk) {
-    const Taps tp = Tap::load(sview + (int64_t)c.m * ec.row_elems + (c.k + 1));
+    const Taps tp = Tap::load(sview + (uint32_t)(c.m * ec.row_elems + c.k + 1));
     const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
     const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
     const float Bv = fmaf(c.fa, r1 - r0, r0);
     const float w = fmaf(c.tf * c.tf, inv_f2, 1.0f);
     const float dB_da = (r1 - r0) * ec.inv_dalpha;
     const float dB_dt = fmaf(c.fa, (tp.s11 - tp.s10) - (tp.s01 - tp.s00), tp.s01 - tp.s00) * ec.inv_dt;
-    // S = sgn * scale * w(t_f) * B(alpha_f, t_f), t_f = sgn * t_raw
-    const float dS_dalpha = c.sgn * scale * w * dB_da;
+    // S = sgn * scale * w(t) * B(alpha, t) with (alpha, t) of the folded line
+    // l' = sgn * l; the two factors sgn cancel in dS/dl, so with
+    // alpha = atan2(l2', l1') and t = -l3' / r:
+    const float dS_dalpha = scale * w * dB_da;
     const float dS_dt = scale * (2.0f * c.tf * inv_f2 * Bv + w * dB_dt);
     const float l1 = (float)c.l1, l2 = (float)c.l2, l3 = (float)c.l3;
     const float rinv = (float)c.rinv;
     const float rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
-    // alpha = atan2(l2, l1), t_raw = -l3 / r
     const float gl1 = gS * (dS_dalpha * (-l2 * rinv2) + dS_dt * (l3 * l1 * rinv3));
     const float gl2 = gS * (dS_dalpha * (l1 * rinv2) + dS_dt * (l3 * l2 * rinv3));
     const float gl3 = gS * (dS_dt * (-rinv));
@@ -100,53 +101,42 @@ __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const View
 }
 
 template <class Tap, class G>
-__global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ sino, const float *__restrict__ vscale,
+__global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ sino,
+                                                      const PairConst<G> *__restrict__ table,
                                                       const ViewGeom *__restrict__ vt,
                                                       const ViewGeomGrad *__restrict__ vg, EvalConsts ec,
                                                       float *__restrict__ pair_grad, double *__restrict__ partials,
                                                       int n_tiles) {
-    __shared__ PairConst<G> lds[kWavesPerBlock][kPairsPerWave];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int hyp_groups = (ec.B + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t total = (int64_t)n_tiles * hyp_groups;
     const int64_t w = xcd_work_item(total);
-    if (w >= total) return;  // whole block
+    if (w >= total) return;
     const int tile = (int)(w / hyp_groups);
     const int hyp = (int)(w % hyp_groups) * kWavesPerBlock + wave;
-    const bool active = hyp < ec.B;
-    const int64_t p0 = (int64_t)tile * kPairsPerWave;
-    const int np = (int)min((int64_t)kPairsPerWave, (int64_t)ec.n_pairs - p0);
+    if (hyp >= ec.B) return;  // no barriers in this kernel
     const ViewGeom *vth = vt + (int64_t)hyp * ec.n_views;
-
-    int my_a = 0, my_b = 0;
-    if (active && lane < np) {
-        pair_from_index(p0 + lane, ec.n_views, my_a, my_b);
-        PairConst<G> pc;
-        pair_setup<G>(vth[my_a], vth[my_b], ec.R_mm, ec.K, pc);
-        pc.va = my_a;
-        pc.vb = my_b;
-        pc.sa = vscale[my_a];
-        pc.sb = vscale[my_b];
-        lds[wave][lane] = pc;
-    }
-    __syncthreads();
-    if (!active) return;
+    const PairConst<G> *tab = table + (int64_t)hyp * ec.n_pairs;
 
     const Tap *base = (const Tap *)sino;
     const float kscale = 2.0f / (float)ec.K;
     double wave_acc = 0.0;
     float mine[13];
     for (int i = 0; i < 13; ++i) mine[i] = 0.0f;
-    for (int q = 0; q < np; ++q) {
-        const PairConst<G> &pc = lds[wave][q];
-        const Tap *sa = base + (int64_t)pc.va * ec.view_elems;
-        const Tap *sb = base + (int64_t)pc.vb * ec.view_elems;
+    for (int q = 0; q < kPairsPerWave; ++q) {
+        int qa, qb;
+        if (!tile_pair(tile, q, ec.n_views, qa, qb)) continue;
+        const PairConst<G> pc = tab[pair_index(qa, qb, ec.n_views)];
+        const Tap *sa = base + (int64_t)qa * ec.view_elems;
+        const Tap *sb = base + (int64_t)qb * ec.view_elems;
         // 1. forward sweep
         float acc = 0.0f;
         int cnt = 0;
+        G sn0, cs0;
+        g_sincos(pc.k0 + (G)lane * pc.dk, &sn0, &cs0);
+        G sn = sn0, cs = cs0;
         for (int k = lane; k < ec.K; k += 64) {
-            G sn, cs;
-            g_sincos(pc.k0 + (G)k * pc.dk, &sn, &cs);
             bool ha, hb;
             const float Sa = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, ha);
             const float Sb = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hb);
@@ -155,6 +145,9 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                 acc = fmaf(diff, diff, acc);
                 ++cnt;
             }
+            const G c2 = cs * pc.rc - sn * pc.rs;
+            sn = sn * pc.rc + cs * pc.rs;
+            cs = c2;
         }
         acc = wave_sum(acc);
         cnt = wave_sum_i(cnt);
@@ -167,9 +160,9 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         if (cnt > 0) {
             // 2. reverse sweep
             const float coef = 2.0f / ((float)cnt * den * den);
+            sn = sn0;
+            cs = cs0;
             for (int k = lane; k < ec.K; k += 64) {
-                G sn, cs;
-                g_sincos(pc.k0 + (G)k * pc.dk, &sn, &cs);
                 const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
                 const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
                 if (ca.hit && cb.hit) {
@@ -182,6 +175,9 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                     // kappa_k = kappa_max ((2k + 1) / K - 1)
                     g[12] = fmaf(gk, (float)(2 * k + 1) * (0.5f * kscale) - 1.0f, g[12]);
                 }
+                const G c2 = cs * pc.rc - sn * pc.rs;
+                sn = sn * pc.rc + cs * pc.rs;
+                cs = c2;
             }
             for (int i = 0; i < 13; ++i) g[i] = wave_sum(g[i]);
         }
@@ -191,36 +187,38 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
     if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
 
     // 3. per-pair tangent sweeps, one pair per lane
-    if (lane < np) {
+    int my_a, my_b;
+    if (tile_pair(tile, lane, ec.n_views, my_a, my_b)) {
         const int64_t gi = (int64_t)my_a + (int64_t)hyp * ec.n_views;
         const int64_t gj = (int64_t)my_b + (int64_t)hyp * ec.n_views;
-        float *out = pair_grad + ((int64_t)hyp * ec.n_pairs + p0 + lane) * 12;
+        float *out = pair_grad + ((int64_t)hyp * ec.n_pairs + pair_index(my_a, my_b, ec.n_views)) * 12;
         for (int dir = 0; dir < 12; ++dir)
             out[dir] = (float)pair_tangent(vth[my_a], vth[my_b], vg[gi], vg[gj], dir, ec.R_mm, mine);
     }
 }
 
 template <class Tap, class G>
-static hipError_t launch_adj_t(const void *sino, const float *vscale, const ViewGeom *vt, const ViewGeomGrad *vg,
+static hipError_t launch_adj_t(const void *sino, const void *table, const ViewGeom *vt, const ViewGeomGrad *vg,
                                EvalConsts ec, float *pair_grad, double *partials, int n_tiles, hipStream_t s) {
     const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
     const int64_t blocks = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL((ecc_adj_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, sino,
-                       vscale, vt, vg, ec, pair_grad, partials, n_tiles);
+    hipLaunchKernelGGL((ecc_adj_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
+                       occupancy_lds_bytes(), s, sino,
+                       (const PairConst<G> *)table, vt, vg, ec, pair_grad, partials, n_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_ecc_adj(const void *sino, const float *view_scale, const ViewGeom *vt, const ViewGeomGrad *vg,
+hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *vt, const ViewGeomGrad *vg,
                           EvalConsts ec, int dtype, float *pair_grad, double *partials, int n_tiles,
                           hipStream_t s) {
     if (ec.geom64) {
-        if (dtype == 0) return launch_adj_t<TapF32, double>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
-        if (dtype == 1) return launch_adj_t<TapBF16, double>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
-        return launch_adj_t<TapF16, double>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+        if (dtype == 0) return launch_adj_t<TapF32, double>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
+        if (dtype == 1) return launch_adj_t<TapBF16, double>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
+        return launch_adj_t<TapF16, double>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
     }
-    if (dtype == 0) return launch_adj_t<TapF32, float>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
-    if (dtype == 1) return launch_adj_t<TapBF16, float>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
-    return launch_adj_t<TapF16, float>(sino, view_scale, vt, vg, ec, pair_grad, partials, n_tiles, s);
+    if (dtype == 0) return launch_adj_t<TapF32, float>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
+    if (dtype == 1) return launch_adj_t<TapBF16, float>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
+    return launch_adj_t<TapF16, float>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,13 +2,15 @@
 //
 // view_setup   one thread per (hypothesis, view): P' = P T(theta) and its
 //              source (Eqs. 4-5), FP64; optionally dP'/dtheta for the adjoint.
-// ecc_fwd      a workgroup = 4 waves = 4 hypotheses of one tile of 64 view
-//              pairs.  Lane j of a wave first builds pair j's geometry in FP64
-//              (baseline, pencil of planes, the two line maps of Eq. 14) into
-//              LDS; the wave then walks its 64 pairs with lanes along the plane
-//              angle kappa: line -> (alpha, t) -> four bilinear taps per view
-//              in one load -> (S_a - S_b)^2 -> wave-shuffle sum (Eq. 15) ->
-//              Cauchy norm (Eq. 16).  No atomics; per-tile FP64 partials.
+// pair_setup   one thread per (hypothesis, pair): the pair's geometry in FP64
+//              (baseline, pencil of planes, the two line maps of Eq. 14) ->
+//              a table of per-plane constants.
+// ecc_fwd      a workgroup = 4 waves = 4 hypotheses of one tile of up to 64
+//              view pairs (8 x 8 view blocks); a wave walks its pairs
+//              (constants read with scalar loads) with lanes along the plane angle kappa: line ->
+//              (alpha, t) -> four bilinear taps per view in one load ->
+//              (S_a - S_b)^2 -> wave-shuffle sum (Eq. 15) -> Cauchy norm
+//              (Eq. 16).  No atomics; per-tile FP64 partials.
 // reduce_cost  fixed-order sum of the tile partials per hypothesis (Eq. 17).
 //
 // Blocks are numbered so that each of the 8 XCDs (which receive workgroups
@@ -17,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "ecc_internal.hpp"
 #include "lookup.hpp"
@@ -96,48 +99,78 @@ hipError_t launch_view_setup(const double *P, const double *intr, const double *
 }
 
 // ---------------------------------------------------------------------------
+size_t pair_const_bytes(bool geom64) { return geom64 ? sizeof(PairConst<double>) : sizeof(PairConst<float>); }
+
+// One thread per (hypothesis, pair): the FP64 per-pair geometry -> the pair's
+// per-plane constants, written to a table the plane kernels read with
+// wave-uniform (scalar) loads.
+template <class G>
+__global__ __launch_bounds__(256) void pair_setup_kernel(const float *__restrict__ vscale,
+                                                         const ViewGeom *__restrict__ vt, EvalConsts ec,
+                                                         PairConst<G> *__restrict__ table) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)ec.B * ec.n_pairs) return;
+    const int hyp = (int)(idx / ec.n_pairs);
+    const int64_t p = idx % ec.n_pairs;
+    int a, b;
+    pair_from_index(p, ec.n_views, a, b);
+    PairConst<G> pc;
+    pair_setup<G>(vt[(int64_t)hyp * ec.n_views + a], vt[(int64_t)hyp * ec.n_views + b], ec.R_mm, ec.K, pc);
+    pc.va = a;
+    pc.vb = b;
+    pc.sa = vscale[a];
+    pc.sb = vscale[b];
+    table[idx] = pc;
+}
+
+template <class G>
+static hipError_t launch_pair_setup_t(const float *vscale, const ViewGeom *vt, EvalConsts ec, void *table,
+                                      hipStream_t s) {
+    const int64_t n = (int64_t)ec.B * ec.n_pairs;
+    hipLaunchKernelGGL(pair_setup_kernel<G>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vscale, vt, ec,
+                       (PairConst<G> *)table);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s) {
+    return ec.geom64 ? launch_pair_setup_t<double>(view_scale, vt, ec, table, s)
+                     : launch_pair_setup_t<float>(view_scale, vt, ec, table, s);
+}
+
+// A wave = one hypothesis x one pair tile; a workgroup = 4 hypotheses of the
+// same tile (they read nearly the same sinogram cells).
 template <class Tap, class G>
-__global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ sino, const float *__restrict__ vscale,
-                                                      const ViewGeom *__restrict__ vt, EvalConsts ec,
+__global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ sino,
+                                                      const PairConst<G> *__restrict__ table, EvalConsts ec,
                                                       float *__restrict__ out_pair, double *__restrict__ partials,
                                                       int n_tiles) {
-    __shared__ PairConst<G> lds[kWavesPerBlock][kPairsPerWave];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int hyp_groups = (ec.B + kWavesPerBlock - 1) / kWavesPerBlock;
     const int64_t total = (int64_t)n_tiles * hyp_groups;
     const int64_t w = xcd_work_item(total);
-    if (w >= total) return;  // whole block
+    if (w >= total) return;
     const int tile = (int)(w / hyp_groups);
     const int hyp = (int)(w % hyp_groups) * kWavesPerBlock + wave;
-    const bool active = hyp < ec.B;
-    const int64_t p0 = (int64_t)tile * kPairsPerWave;
-    const int np = (int)min((int64_t)kPairsPerWave, (int64_t)ec.n_pairs - p0);
-
-    if (active && lane < np) {
-        int a, b;
-        pair_from_index(p0 + lane, ec.n_views, a, b);
-        PairConst<G> pc;
-        pair_setup<G>(vt[(int64_t)hyp * ec.n_views + a], vt[(int64_t)hyp * ec.n_views + b], ec.R_mm, ec.K, pc);
-        pc.va = a;
-        pc.vb = b;
-        pc.sa = vscale[a];
-        pc.sb = vscale[b];
-        lds[wave][lane] = pc;
-    }
-    __syncthreads();
-    if (!active) return;
+    if (hyp >= ec.B) return;  // no barriers in this kernel
+    const PairConst<G> *tab = table + (int64_t)hyp * ec.n_pairs;
 
     const Tap *base = (const Tap *)sino;
     double wave_acc = 0.0;
-    for (int q = 0; q < np; ++q) {
-        const PairConst<G> &pc = lds[wave][q];
-        const Tap *sa = base + (int64_t)pc.va * ec.view_elems;
-        const Tap *sb = base + (int64_t)pc.vb * ec.view_elems;
+    for (int q = 0; q < kPairsPerWave; ++q) {
+        int a, b;
+        if (!tile_pair(tile, q, ec.n_views, a, b)) continue;
+        const int64_t p = pair_index(a, b, ec.n_views);
+        const PairConst<G> pc = tab[p];
+        const Tap *sa = base + (int64_t)a * ec.view_elems;
+        const Tap *sb = base + (int64_t)b * ec.view_elems;
         float acc = 0.0f;
         int cnt = 0;
+        // plane angle of this lane, advanced by one wave step (64 dk) per
+        // iteration through the rotation (rc, rs)
+        G sn, cs;
+        g_sincos(pc.k0 + (G)lane * pc.dk, &sn, &cs);
         for (int k = lane; k < ec.K; k += 64) {
-            G sn, cs;
-            g_sincos(pc.k0 + (G)k * pc.dk, &sn, &cs);
             bool hit_a, hit_b;
             const float Sa = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, hit_a);
             const float Sb = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hit_b);
@@ -146,37 +179,61 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
                 acc = fmaf(diff, diff, acc);
                 ++cnt;
             }
+            const G c2 = cs * pc.rc - sn * pc.rs;
+            sn = sn * pc.rc + cs * pc.rs;
+            cs = c2;
         }
         acc = wave_sum(acc);
         cnt = wave_sum_i(cnt);
         const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
         const float e = ec.inv_c > 0.0f ? d / (1.0f + d * ec.inv_c) : d;
-        if (out_pair && lane == 0) out_pair[(int64_t)hyp * ec.n_pairs + p0 + q] = e;
+        if (out_pair && lane == 0) out_pair[(int64_t)hyp * ec.n_pairs + p] = e;
         wave_acc += (double)e;
     }
     if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
 }
 
+// Occupancy cap of the plane kernels: workgroups per CU, enforced through an
+// unused dynamic LDS allocation (160 KB per CU).  More resident waves than
+// this widen the set of pair tiles in flight per XCD beyond what its L2 can
+// hold, and L2 misses grow faster than latency hiding gains.
+static int blocks_per_cu_cap() {
+    static int cap = [] {
+        const char *e = getenv("ECC_BLOCKS_PER_CU");
+        const int v = e ? atoi(e) : kDefaultBlocksPerCU;
+        return v < 0 ? 0 : v;
+    }();
+    return cap;
+}
+
+size_t occupancy_lds_bytes() {
+    const int cap = blocks_per_cu_cap();
+    if (cap <= 0) return 0;
+    size_t b = (160u * 1024u) / (size_t)cap;
+    b = (b / 1024) * 1024;
+    return b > 65536 ? 65536 : b;
+}
+
 template <class Tap, class G>
-static hipError_t launch_fwd_t(const void *sino, const float *vscale, const ViewGeom *vt, EvalConsts ec,
-                               float *out_pair, double *partials, int n_tiles, hipStream_t s) {
+static hipError_t launch_fwd_t(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
+                               int n_tiles, hipStream_t s) {
     const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
     const int64_t blocks = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, s, sino,
-                       vscale, vt, ec, out_pair, partials, n_tiles);
+    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
+                       occupancy_lds_bytes(), s, sino, (const PairConst<G> *)table, ec, out_pair, partials, n_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_ecc_fwd(const void *sino, const float *view_scale, const ViewGeom *vt, EvalConsts ec, int dtype,
-                          float *out_pair, double *partials, int n_tiles, hipStream_t s) {
+hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
+                          double *partials, int n_tiles, hipStream_t s) {
     if (ec.geom64) {
-        if (dtype == 0) return launch_fwd_t<TapF32, double>(sino, view_scale, vt, ec, out_pair, partials, n_tiles, s);
-        if (dtype == 1) return launch_fwd_t<TapBF16, double>(sino, view_scale, vt, ec, out_pair, partials, n_tiles, s);
-        return launch_fwd_t<TapF16, double>(sino, view_scale, vt, ec, out_pair, partials, n_tiles, s);
+        if (dtype == 0) return launch_fwd_t<TapF32, double>(sino, table, ec, out_pair, partials, n_tiles, s);
+        if (dtype == 1) return launch_fwd_t<TapBF16, double>(sino, table, ec, out_pair, partials, n_tiles, s);
+        return launch_fwd_t<TapF16, double>(sino, table, ec, out_pair, partials, n_tiles, s);
     }
-    if (dtype == 0) return launch_fwd_t<TapF32, float>(sino, view_scale, vt, ec, out_pair, partials, n_tiles, s);
-    if (dtype == 1) return launch_fwd_t<TapBF16, float>(sino, view_scale, vt, ec, out_pair, partials, n_tiles, s);
-    return launch_fwd_t<TapF16, float>(sino, view_scale, vt, ec, out_pair, partials, n_tiles, s);
+    if (dtype == 0) return launch_fwd_t<TapF32, float>(sino, table, ec, out_pair, partials, n_tiles, s);
+    if (dtype == 1) return launch_fwd_t<TapBF16, float>(sino, table, ec, out_pair, partials, n_tiles, s);
+    return launch_fwd_t<TapF16, float>(sino, table, ec, out_pair, partials, n_tiles, s);
 }
 
 // ---------------------------------------------------------------------------

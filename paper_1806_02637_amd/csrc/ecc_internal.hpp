@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct ecc_ctx;
+
 namespace ecc {
 
 // ---------------------------------------------------------------------------
@@ -82,17 +84,27 @@ hipError_t launch_sino_read(const void *sino, const float *view_scale, SinoLayou
 
 hipError_t launch_view_setup(const double *P, const double *intr, const double *theta, int B, int n_views,
                              ViewGeom *vt, ViewGeomGrad *vg, hipStream_t s);
-hipError_t launch_ecc_fwd(const void *sino, const float *view_scale, const ViewGeom *vt, EvalConsts ec,
-                          int dtype, float *out_pair, double *partials, int n_tiles, hipStream_t s);
-hipError_t launch_ecc_adj(const void *sino, const float *view_scale, const ViewGeom *vt, const ViewGeomGrad *vg,
+// per-pair constant table: [B][n_pairs] PairConst<float> or PairConst<double>
+size_t pair_const_bytes(bool geom64);
+hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s);
+hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
+                          double *partials, int n_tiles, hipStream_t s);
+hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *vt, const ViewGeomGrad *vg,
                           EvalConsts ec, int dtype, float *pair_grad, double *partials, int n_tiles,
                           hipStream_t s);
 hipError_t launch_reduce_cost(const double *partials, int n_tiles, int B, double *out_cost, hipStream_t s);
 hipError_t launch_reduce_grad(const float *pair_grad, int B, int n_views, float *grad, hipStream_t s);
 
+// Engine services shared with the server (engine.hip).
+int ctx_device(struct ::ecc_ctx *ctx);
+int32_t set_error(int32_t code, const char *fmt, ...);
+
 constexpr int kPairsPerWave = 64;
 // zero border (pixels) around the weighted projections read by the line sums
 constexpr int kImgPad = 3;
 constexpr int kWavesPerBlock = 4;
+// default cap on resident plane-kernel workgroups per CU (0 = no cap)
+constexpr int kDefaultBlocksPerCU = 4;
+size_t occupancy_lds_bytes();
 
 }  // namespace ecc

@@ -109,11 +109,14 @@ Scan *find_scan(ecc_ctx *ctx, int32_t id) {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-int n_tiles_for(int64_t n_pairs) { return (int)((n_pairs + kPairsPerWave - 1) / kPairsPerWave); }
+int n_tiles_for(int n_views) {
+    const int nb = (n_views + 7) / 8;  // 8-view blocks, tiles = block pairs I <= J
+    return nb * (nb + 1) / 2;
+}
 
 // Workspace layout of an evaluation.
 struct Workspace {
-    uint64_t vt_off, vg_off, part_off, pgrad_off, total;
+    uint64_t vt_off, vg_off, table_off, part_off, pgrad_off, total;
 };
 
 Workspace workspace_layout(const Scan *s, int B, bool grad) {
@@ -124,8 +127,10 @@ Workspace workspace_layout(const Scan *s, int B, bool grad) {
     off += align256(sizeof(ViewGeom) * (uint64_t)B * s->n_views);
     w.vg_off = off;
     if (grad) off += align256(sizeof(ViewGeomGrad) * (uint64_t)B * s->n_views);
+    w.table_off = off;  // sized for the FP64 plane-geometry form, the larger one
+    off += align256(pair_const_bytes(true) * (uint64_t)B * n_pairs);
     w.part_off = off;
-    off += align256(sizeof(double) * (uint64_t)B * n_tiles_for(n_pairs));
+    off += align256(sizeof(double) * (uint64_t)B * n_tiles_for(s->n_views));
     w.pgrad_off = off;
     if (grad) off += align256(sizeof(float) * 12ull * (uint64_t)B * n_pairs);
     w.total = off;
@@ -187,6 +192,19 @@ EvalConsts make_consts(const Scan *s, int B, const ecc_eval_params *prm) {
 }
 
 }  // namespace
+
+namespace ecc {
+int ctx_device(ecc_ctx *ctx) { return ctx->device; }
+int32_t set_error(int32_t code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+}  // namespace ecc
 
 extern "C" {
 
@@ -342,7 +360,7 @@ static ecc_status install_sinograms(ecc_ctx *ctx, Scan *s, int32_t n_alpha, int3
 ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, double ds_px,
                                     int32_t dtype, void *stream) {
     if (!ctx) return fail(ECC_E_ARG, "null context");
-    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536)
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 31))
         return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
     if (!(ds_px > 0.0) || ds_px > 1.0) return fail(ECC_E_ARG, "ds_px must be in (0, 1]");
     if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
@@ -357,7 +375,7 @@ ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alp
 ecc_status ecc_scan_set_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, const float *sino,
                                   int32_t sino_on_device, int32_t dtype) {
     if (!ctx || !sino) return fail(ECC_E_ARG, "null argument");
-    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536)
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 31))
         return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
     if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
     DeviceGuard g(ctx->device);
@@ -453,9 +471,11 @@ ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *thet
     ViewGeom *vt = (ViewGeom *)(ws + w.vt_off);
     double *partials = (double *)(ws + w.part_off);
     const EvalConsts ec = make_consts(s, B, params);
-    const int n_tiles = n_tiles_for(ec.n_pairs);
+    const int n_tiles = n_tiles_for(ec.n_views);
+    void *table = ws + w.table_off;
     HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, nullptr, hs));
-    HIP_TRY(launch_ecc_fwd(s->sino_dev, s->scale_dev, vt, ec, s->layout.dtype, out_pair_dev, partials, n_tiles, hs));
+    HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs));
+    HIP_TRY(launch_ecc_fwd(s->sino_dev, table, ec, s->layout.dtype, out_pair_dev, partials, n_tiles, hs));
     HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
     return ok();
 }
@@ -481,9 +501,11 @@ ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double 
     double *partials = (double *)(ws + w.part_off);
     float *pgrad = out_pair_grad_dev ? out_pair_grad_dev : (float *)(ws + w.pgrad_off);
     const EvalConsts ec = make_consts(s, B, params);
-    const int n_tiles = n_tiles_for(ec.n_pairs);
+    const int n_tiles = n_tiles_for(ec.n_views);
+    void *table = ws + w.table_off;
     HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, vg, hs));
-    HIP_TRY(launch_ecc_adj(s->sino_dev, s->scale_dev, vt, vg, ec, s->layout.dtype, pgrad, partials, n_tiles, hs));
+    HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs));
+    HIP_TRY(launch_ecc_adj(s->sino_dev, table, vt, vg, ec, s->layout.dtype, pgrad, partials, n_tiles, hs));
     HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
     HIP_TRY(launch_reduce_grad(pgrad, B, s->n_views, grad_dev, hs));
     return ok();

@@ -9,19 +9,20 @@
 #include <stdint.h>
 
 #include "ecc_internal.hpp"
+#include "poly_coeffs.hpp"
 
 namespace ecc {
 
 // Per-plane constants of one view pair, built in FP64 and kept in LDS.
 //   ha, hb: line maps of views a and b, l = H (cos kappa, sin kappa) with the
 //           line's offset about the principal point (H column-major);
-//   k0, dk: kappa_k = k0 + k dk;
+//   k0, dk: kappa_k = k0 + k dk; rc, rs: cos / sin of 64 dk (one wave step);
 //   inv_f2a/b: 1 / f^2 of the views (Grangeat weight 1 + t^2 / f^2);
 //   sa, sb: storage scales of the two views' sinograms; va, vb: view ids.
 template <class G>
 struct PairConst {
     G ha[6], hb[6];
-    G k0, dk;
+    G k0, dk, rc, rs;
     float inv_f2a, inv_f2b, sa, sb;
     int va, vb;
 };
@@ -63,63 +64,87 @@ struct TapF16 {
 };
 
 // ---- precision-generic helpers ----------------------------------------------
-__device__ __forceinline__ void g_sincos(float x, float *s, float *c) { sincosf(x, s, c); }
+// FP32: fitted polynomials (poly_coeffs.hpp) -- the plane angle only selects
+// which plane of the pencil is sampled, identically for both views, and the
+// line angle enters the lookup through an FP32 fraction anyway.  FP64: the
+// library functions.
+__device__ __forceinline__ void g_sincos(float x, float *s, float *c) {
+    // |x| <= pi/2 (plane angles of the pencil)
+    const float x2 = x * x;
+    float ps = kSin[5], pc = kCos[6];
+#pragma unroll
+    for (int i = 4; i >= 0; --i) ps = fmaf(ps, x2, kSin[i]);
+#pragma unroll
+    for (int i = 5; i >= 0; --i) pc = fmaf(pc, x2, kCos[i]);
+    *s = ps * x;
+    *c = pc;
+}
 __device__ __forceinline__ void g_sincos(double x, double *s, double *c) { sincos(x, s, c); }
-__device__ __forceinline__ float g_atan2(float y, float x) { return atan2f(y, x); }
-__device__ __forceinline__ double g_atan2(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ float g_rsqrt(float x) { return 1.0f / sqrtf(x); }
+
+// Angle of (x, y) for y >= 0, in [0, pi].
+__device__ __forceinline__ float g_atan2_upper(float y, float x) {
+    const float ax = fabsf(x);
+    const float mx = fmaxf(ax, y), mn = fminf(ax, y);
+    const float z = mn * __builtin_amdgcn_rcpf(mx);
+    const float z2 = z * z;
+    float p = kAtan[7];
+#pragma unroll
+    for (int i = 6; i >= 0; --i) p = fmaf(p, z2, kAtan[i]);
+    float a = p * z;
+    a = y > ax ? 1.57079632679489662f - a : a;
+    return x < 0.0f ? 3.14159265358979324f - a : a;
+}
+__device__ __forceinline__ double g_atan2_upper(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float g_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double g_rsqrt(double x) { return 1.0 / sqrt(x); }
 
 template <class G> struct GConst;
 template <> struct GConst<float> {
-    static __device__ __forceinline__ float pi() { return 3.14159265358979323846f; }
     static __device__ __forceinline__ float t_max(const EvalConsts &e) { return e.t_max; }
     static __device__ __forceinline__ float inv_dt(const EvalConsts &e) { return e.inv_dt; }
     static __device__ __forceinline__ float inv_dalpha(const EvalConsts &e) { return e.inv_dalpha; }
 };
 template <> struct GConst<double> {
-    static __device__ __forceinline__ double pi() { return 3.14159265358979323846; }
     static __device__ __forceinline__ double t_max(const EvalConsts &e) { return e.t_max_d; }
     static __device__ __forceinline__ double inv_dt(const EvalConsts &e) { return e.inv_dt_d; }
     static __device__ __forceinline__ double inv_dalpha(const EvalConsts &e) { return e.inv_dalpha_d; }
 };
 
-// Sinogram coordinates of the image line l (pixels, offset about the
-// principal point) and the lookup position.
+__device__ __forceinline__ float g_flip(float x, bool f) { return f ? -x : x; }
+__device__ __forceinline__ double g_flip(double x, bool f) { return f ? -x : x; }
+
+// Sinogram coordinates of an image line l (pixels, offset about the principal
+// point).  The line's orientation is folded so that alpha = atan2(l2, l1)
+// lies in [0, pi): when l2 < 0 (or l2 = 0 with l1 < 0) the line is negated,
+// which maps (alpha, t) to (alpha + pi, -t), and the sinogram's odd symmetry
+// contributes the sign sgn = -1.
 template <class G>
 struct LineCoord {
-    G l1, l2, l3, r2, rinv, t;  // t after folding
-    float sgn;                   // -1 when alpha was folded by pi
-    float fa, ft, tf;            // bilinear fractions, folded t in FP32
-    int m, k;                    // floor cell (clamped for memory safety)
+    G l1, l2, l3, rinv;  // folded line, 1/|(l1, l2)|
+    float sgn;           // -1 when the line was folded
+    float fa, ft, tf;    // bilinear fractions, folded t (FP32)
+    int m, k;            // floor cell (clamped for memory safety)
     bool hit;
 };
 
 template <class G>
 __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, const EvalConsts &ec) {
     LineCoord<G> c;
-    c.l1 = h[0] * cs + h[3] * sn;
-    c.l2 = h[1] * cs + h[4] * sn;
-    c.l3 = h[2] * cs + h[5] * sn;
-    c.r2 = c.l1 * c.l1 + c.l2 * c.l2;
-    c.rinv = g_rsqrt(c.r2);
-    G alpha = g_atan2(c.l2, c.l1);
-    G t = -c.l3 * c.rinv;
-    c.sgn = 1.0f;
-    const G pi = GConst<G>::pi();
-    if (alpha < (G)0) {
-        alpha += pi;
-        t = -t;
-        c.sgn = -1.0f;
-    } else if (alpha >= pi) {
-        alpha -= pi;
-        t = -t;
-        c.sgn = -1.0f;
-    }
-    c.t = t;
-    // closed detector rectangle of pixel edges: |t| <= (W/2)|cos a| + (H/2)|sin a|
-    const G sup = ((G)ec.half_w * fabs(c.l1) + (G)ec.half_h * fabs(c.l2)) * c.rinv;
-    c.hit = (c.r2 > (G)0) && (fabs(t) <= sup);
+    G l1 = h[0] * cs + h[3] * sn;
+    G l2 = h[1] * cs + h[4] * sn;
+    G l3 = h[2] * cs + h[5] * sn;
+    const bool fold = (l2 < (G)0) | ((l2 == (G)0) & (l1 < (G)0));  // no short-circuit: stays branch-free
+    c.l1 = g_flip(l1, fold);
+    c.l2 = g_flip(l2, fold);
+    c.l3 = g_flip(l3, fold);
+    c.sgn = fold ? -1.0f : 1.0f;
+    const G r2 = c.l1 * c.l1 + c.l2 * c.l2;
+    c.rinv = g_rsqrt(r2);
+    const G alpha = g_atan2_upper(fabs(c.l2), c.l1);
+    const G t = -c.l3 * c.rinv;
+    // closed detector rectangle of pixel edges:
+    // |t| <= (W/2)|cos a| + (H/2)|sin a|  <=>  |l3| <= (W/2)|l1| + (H/2)|l2|
+    c.hit = (r2 > (G)0) && (fabs(c.l3) <= (G)ec.half_w * fabs(c.l1) + (G)ec.half_h * fabs(c.l2));
     const G aa = alpha * GConst<G>::inv_dalpha(ec);
     const G mf = fmin(fmax(floor(aa), (G)0), (G)(ec.n_alpha - 1));
     const G tau = (t + GConst<G>::t_max(ec)) * GConst<G>::inv_dt(ec);
@@ -136,7 +161,8 @@ __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, con
 template <class Tap, class G>
 __device__ __forceinline__ float sample_at(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec,
                                            float inv_f2, float scale) {
-    const Taps tp = Tap::load(sview + (int64_t)c.m * ec.row_elems + (c.k + 1));
+    // a view holds < 2^31 elements: 32-bit element offset
+    const Taps tp = Tap::load(sview + (uint32_t)(c.m * ec.row_elems + c.k + 1));
     const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
     const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
     const float B = fmaf(c.fa, r1 - r0, r0);

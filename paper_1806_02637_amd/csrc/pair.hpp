@@ -49,6 +49,10 @@ __device__ __forceinline__ void pair_setup(const ViewGeom &A, const ViewGeom &Bv
     const double dk = 2.0 * km / K;
     pc.k0 = (G)(-km + 0.5 * dk);
     pc.dk = (G)dk;
+    double rs, rc;
+    sincos(64.0 * dk, &rs, &rc);
+    pc.rc = (G)rc;
+    pc.rs = (G)rs;
     pc.inv_f2a = (float)(1.0 / (A.f * A.f));
     pc.inv_f2b = (float)(1.0 / (Bv.f * Bv.f));
 }
@@ -60,6 +64,44 @@ __device__ __forceinline__ float wave_sum(float x) {
 __device__ __forceinline__ int wave_sum_i(int x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     return x;
+}
+
+// Pair tiles: the views are cut into blocks of kViewBlock consecutive views and
+// a tile is one (block I, block J >= I) product -- up to 8 x 8 pairs (I < J)
+// or the 28 pairs inside one block (I == J).  The 8 neighbouring sources of a
+// block give similar pencils in each view of the other block, so a tile
+// touches 16 views' sinograms with high reuse.  Tiles run row by row
+// (I fixed, J increasing).
+constexpr int kViewBlock = 8;
+
+__host__ __device__ inline int n_view_blocks(int n_views) { return (n_views + kViewBlock - 1) / kViewBlock; }
+__host__ __device__ inline int n_pair_tiles(int n_views) {
+    const int nb = n_view_blocks(n_views);
+    return nb * (nb + 1) / 2;
+}
+
+// Pair q (0..63) of tile `tile`; false when the slot is empty.
+__device__ __forceinline__ bool tile_pair(int tile, int q, int n_views, int &a, int &b) {
+    const int nb = n_view_blocks(n_views);
+    // block row I of the upper triangle (diagonal included)
+    const double m = 2.0 * nb + 1.0;
+    int I = (int)floor(0.5 * (m - sqrt(m * m - 8.0 * (double)tile)));
+    if (I < 0) I = 0;
+    if (I > nb - 1) I = nb - 1;
+    while (I > 0 && I * nb - I * (I - 1) / 2 > tile) --I;
+    while (I < nb - 1 && (I + 1) * nb - (I + 1) * I / 2 <= tile) ++I;
+    const int J = tile - (I * nb - I * (I - 1) / 2) + I;
+    if (I < J) {
+        a = I * kViewBlock + q / kViewBlock;
+        b = J * kViewBlock + q % kViewBlock;
+    } else {
+        if (q >= kViewBlock * (kViewBlock - 1) / 2) return false;
+        int i, j;
+        pair_from_index(q, kViewBlock, i, j);
+        a = I * kViewBlock + i;
+        b = I * kViewBlock + j;
+    }
+    return a < n_views && b < n_views;
 }
 
 // Logical work item of a block under the XCD-aware numbering.

@@ -5,13 +5,10 @@
 //  1. sino_weight: radial (cosine) weight f / sqrt(f^2 + x^2 + y^2) on pixel
 //     centres, written twice: row-major and transposed, both with a 3-pixel
 //     zero border so that line samples need no bounds checks.
-//  2. sino_radon: one thread per (view, alpha_m, t_k) cell sums bilinear
+//  2. sino_radon: 16 lanes per (view, alpha_m, t_k) cell sum bilinear
 //     samples along its line, only over the stretch where they can be
-//     non-zero.  Lines closer to horizontal read the transposed copy, so the
-//     64 lanes of a wave (consecutive t) always step along a contiguous
-//     image axis.  Sample positions are formed per 32-sample chunk from an
-//     FP64 start split into integer + FP32 fraction; chunk sums are FP32,
-//     the line total FP64.
+//     non-zero; a wave covers 4 neighbouring lines x 16 consecutive samples so
+//     its gathers stay within a small image patch (see the kernel).
 //  3. sino_store: central t-difference of the line integrals, the pad row
 //     at alpha = pi from the odd symmetry, conversion to the storage type and
 //     the row-interleaved layout the consistency kernels read.
@@ -86,20 +83,30 @@ __device__ __forceinline__ void clip_axis(double c0, double dc, double lo, doubl
 
 typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
+// Block = 4 waves; wave = 4 detector lines (consecutive t) x 16 lanes along
+// each line.  Lane (ti, si) takes samples j = j0 + si + 16 i of line ti, so
+// one gather of the wave touches a compact patch of about 6 x 8 pixels
+// whatever the angle; the image copy is chosen so that the lines run along
+// its contiguous axis.  Per lane the sample position is kept as an integer
+// pixel plus an FP32 fraction renormalised every step (drift < 1e-4 px over
+// a line); per-lane sums are flushed from FP32 to FP64 every 32 steps and the
+// 16 lane sums of a line are added in a fixed butterfly order.
 __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict__ gw, const float *__restrict__ gwT,
                                                          const double *__restrict__ intr, int W, int H,
                                                          int n_alpha, int n_t, double t_max, double dt, double ds,
                                                          int n_s, double *__restrict__ G) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ti = lane >> 4, si = lane & 15;
+    const int k = (blockIdx.x * 4 + wave) * 4 + ti;
     const int m = blockIdx.y, v = blockIdx.z;
-    if (k >= n_t) return;
     const double u0 = intr[3 * v + 1], v0 = intr[3 * v + 2];
     const double alpha = m * (kPi / n_alpha);
     double sa, ca;
     sincos(alpha, &sa, &ca);
-    const double t = -t_max + k * dt;
-    // sample at s: (x, y) = (u0 + t ca - s sa, v0 + t sa + s ca)
-    const bool trans = fabs(sa) > fabs(ca);  // uniform over the block
+    const double t = -t_max + (k < n_t ? k : 0) * dt;
+    // sample at s: (x, y) = (u0 + t ca - s sa, v0 + t sa + s ca); the line
+    // direction (-sa, ca) is closer to the x axis when |sa| > |ca|
+    const bool trans = fabs(sa) <= fabs(ca);  // uniform over the block
     double p0, q0, dp, dq;
     int P_ext, Q_ext;
     const float *img;
@@ -125,40 +132,56 @@ __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict
     clip_axis(p0, dp, -1.0, (double)P_ext, s_lo, s_hi);
     clip_axis(q0, dq, -1.0, (double)Q_ext, s_lo, s_hi);
     const double c = 0.5 * (n_s - 1);
-    double acc = 0.0;
-    if (s_lo <= s_hi) {
+    int j_lo = 1, j_hi = 0;  // empty
+    if (k < n_t && s_lo <= s_hi) {
         // one extra sample (ds <= 1 px) on each side absorbs rounding of the
         // clip: samples stay within 2 px of the image, inside the zero border
-        const int j_lo = max(0, (int)ceil(s_lo / ds + c) - 1);
-        const int j_hi = min(n_s - 1, (int)floor(s_hi / ds + c) + 1);
-        const float dpf = (float)(dp * ds), dqf = (float)(dq * ds);
-        for (int j0 = j_lo; j0 <= j_hi; j0 += 32) {
-            const double s = (j0 - c) * ds;
-            const double pp = p0 + s * dp, qq = q0 + s * dq;
-            const double pfl = floor(pp), qfl = floor(qq);
-            const float fp = (float)(pp - pfl), fq = (float)(qq - qfl);
-            const float *base = img + (int64_t)((int)qfl + kImgPad) * pitch + ((int)pfl + kImgPad);
-            const int cnt = min(32, j_hi - j0 + 1);
-            float part = 0.0f;
-#pragma unroll 8
-            for (int i = 0; i < 32; ++i) {
-                if (i < cnt) {
-                    const float x = fmaf((float)i, dpf, fp);
-                    const float y = fmaf((float)i, dqf, fq);
-                    const float xf = floorf(x), yf = floorf(y);
-                    const float fx = x - xf, fy = y - yf;
-                    const float *ptr = base + (int)yf * pitch + (int)xf;
-                    const float2_a4 top = *(const float2_a4 *)ptr;
-                    const float2_a4 bot = *(const float2_a4 *)(ptr + pitch);
-                    const float a = fmaf(fx, top.y - top.x, top.x);
-                    const float b = fmaf(fx, bot.y - bot.x, bot.x);
-                    part += fmaf(fy, b - a, a);
-                }
-            }
-            acc += (double)part;
-        }
+        j_lo = max(0, (int)ceil(s_lo / ds + c) - 1);
+        j_hi = min(n_s - 1, (int)floor(s_hi / ds + c) + 1);
     }
-    G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
+    // wave-uniform sweep over the union of the four lines' ranges
+    int w_lo = j_lo <= j_hi ? j_lo : 0x7fffffff, w_hi = j_lo <= j_hi ? j_hi : -1;
+    for (int off = 16; off < 64; off <<= 1) {
+        w_lo = min(w_lo, __shfl_xor(w_lo, off, 64));
+        w_hi = max(w_hi, __shfl_xor(w_hi, off, 64));
+    }
+    double acc = 0.0;
+    if (w_lo <= w_hi) {
+        const int j_first = w_lo + si;
+        const double s = (j_first - c) * ds;
+        const double pp = p0 + s * dp, qq = q0 + s * dq;
+        const double pfl = floor(pp), qfl = floor(qq);
+        float fp = (float)(pp - pfl), fq = (float)(qq - qfl);
+        int ip = (int)pfl + kImgPad, iq = (int)qfl + kImgPad;
+        const float sp = (float)(16.0 * ds * dp), sq = (float)(16.0 * ds * dq);
+        float part = 0.0f;
+        int n_in_part = 0;
+        for (int j = j_first; j - si <= w_hi; j += 16) {
+            if (j >= j_lo && j <= j_hi) {
+                const float *ptr = img + (int64_t)iq * pitch + ip;
+                const float2_a4 top = *(const float2_a4 *)ptr;
+                const float2_a4 bot = *(const float2_a4 *)(ptr + pitch);
+                const float a = fmaf(fp, top.y - top.x, top.x);
+                const float b = fmaf(fp, bot.y - bot.x, bot.x);
+                part += fmaf(fq, b - a, a);
+            }
+            fp += sp;
+            fq += sq;
+            const float flp = floorf(fp), flq = floorf(fq);
+            fp -= flp;
+            fq -= flq;
+            ip += (int)flp;
+            iq += (int)flq;
+            if (++n_in_part == 32) {
+                acc += (double)part;
+                part = 0.0f;
+                n_in_part = 0;
+            }
+        }
+        acc += (double)part;
+    }
+    for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if (si == 0 && k < n_t) G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
 }
 
 hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *intr, int n_views, int W, int H,
@@ -166,7 +189,7 @@ hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *in
     const double t_max = 0.5 * sqrt((double)W * W + (double)H * H);
     const double dt = 2.0 * t_max / (n_t - 1);
     const int n_s = 2 * (int)ceil(t_max / ds) + 1;
-    dim3 grid((n_t + 255) / 256, n_alpha, n_views);
+    dim3 grid((n_t + 15) / 16, n_alpha, n_views);  // 16 lines per block
     hipLaunchKernelGGL(sino_radon_kernel, grid, dim3(256), 0, s, gw, gwT, intr, W, H, n_alpha, n_t, t_max, dt, ds,
                        n_s, G);
     return hipGetLastError();

@@ -1,0 +1,153 @@
+"""Adjoint (d cost / d theta) of the HIP path against the oracle's exact
+dual-number gradient, against central differences, and through
+torch.autograd.
+
+Tolerances: the per-plane reverse sweep runs in FP32 (the per-pair tangent
+sweeps in FP64), so per-pair gradient 12-vectors agree with the oracle to
+~1e-4 of their norm; the summed gradient to 2e-4 relative L2 (measured
+3e-6, c = inf).  Central differences of the cost (h = 1e-3 deg / mm) are not
+the derivative of a piecewise-bilinear cost: lines cross bilinear cell
+boundaries inside [-h, h] (a 1e-3 deg turn moves a line by ~0.03 px at the
+248-view resolution) and the FP32 cost's rounding is divided by 2h; measured
+1.4e-2 relative L2 at the 248-view workload, bounded here at 3e-2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.ecc import as_rows, ecc_pair_grad, pair_index
+from paper_1806_02637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+
+    from paper_1806_02637_amd import engine
+
+    assert torch.cuda.is_available()
+    e = engine.Engine(0)
+    yield e
+    e.close()
+
+
+def test_gradient_matches_oracle_small16(eng, small16):
+    _say("case: adjoint small16 vs oracle (oracle sinograms)")
+    s = small16
+    g = s["geom"]
+    scan = eng.load_scan(s["P"], s["intr"], s["images"])
+    scan.set_sinograms(s["sino"].data.astype(np.float32), "f32")
+    sino32 = oracle.FullSinograms(s["sino"].data.astype(np.float32).astype(np.float64), s["grid"])
+    thetas = inputs.random_motion(1001, 3, g.n_views)
+    for c in (math.inf, 30.0):
+        params = oracle.EccParams(s["params"].K, s["params"].R_mm, c)
+        cost, grad, pg = scan.cost_grad(thetas, params.K, params.R_mm, c=c, with_pair_grads=True)
+        cost_f = scan.cost(thetas, params.K, params.R_mm, c=c)
+        # the adjoint kernel's forward sweep repeats the forward kernel's arithmetic
+        assert np.allclose(cost.cpu().numpy(), cost_f.cpu().numpy(), rtol=1e-6, atol=0)
+        grad, pg = grad.cpu().numpy(), pg.cpu().numpy()
+        for h in range(thetas.shape[0]):
+            c_ref, g_ref, pg_ref = oracle.ecc_grad(s["P"], s["intr"], thetas[h], s["grid"], sino32, params)
+            err = np.linalg.norm(grad[h] - g_ref) / np.linalg.norm(g_ref)
+            _say(f"  c={c} hyp {h}: grad rel L2 {err:.2e}")
+            assert err <= 2e-4
+            nrm = np.linalg.norm(pg_ref, axis=1) + 1e-30
+            perr = np.linalg.norm(pg[h] - pg_ref, axis=1) / nrm
+            assert np.quantile(perr, 0.99) <= 1e-3 and perr.max() <= 1e-2, perr.max()
+    scan.free()
+
+
+def test_gradient_sampled_pairs_and_fd_adj248(eng):
+    # the 248-view adjoint workload at its full size: per-pair gradients of
+    # sampled pairs against the oracle (lazy sinograms from the same
+    # images), and the summed gradient against central differences of the
+    # GPU cost (FP64 plane geometry) for sampled parameters
+    import torch
+
+    _say("case: adjoint adj248 sampled pairs + central differences")
+    w = inputs.WORKLOADS["adj248"]
+    g = w.geom
+    P, intr = g.projection_matrices(), g.intrinsics()
+    imgs = inputs.project(g, w.phantom(), device="cuda", as_tensor=True)
+    scan = eng.load_scan(P, intr, imgs)
+    scan.build_sinograms(w.n_alpha, w.n_t, w.ds_px, "f32")
+    theta = w.motion(1)
+    cost, grad, pg = scan.cost_grad(theta, w.K, w.R_mm, with_pair_grads=True)
+    grad, pg = grad.cpu().numpy()[0], pg.cpu().numpy()[0]
+    # per-pair 12-vectors sum to the per-view gradient (scatter check)
+    acc = np.zeros((g.n_views, 6))
+    for a in range(g.n_views):
+        for b in range(a + 1, g.n_views):
+            p = pair_index(a, b, g.n_views)
+            acc[a] += pg[p, :6]
+            acc[b] += pg[p, 6:]
+    assert np.allclose(acc, grad, rtol=1e-5, atol=1e-6 * np.abs(grad).max())
+    # oracle per-pair gradients on sampled pairs
+    rng = np.random.default_rng(21)
+    sel = []
+    while len(sel) < 10:
+        a, b = sorted(rng.choice(g.n_views, 2, replace=False).tolist())
+        sel.append((a, b))
+    views = sorted({v for ab in sel for v in ab})
+    host = {v: imgs[v].cpu().numpy() for v in views}
+
+    class Imgs:
+        def __getitem__(self, v):
+            return host[v]
+
+    grid = oracle.SinoGrid(g.W, g.H, w.n_alpha, w.n_t, w.ds_px)
+    lazy = oracle.LazySinograms(Imgs(), grid, intr)
+    params = oracle.EccParams(w.K, w.R_mm)
+    for a, b in sel:
+        _, gref = ecc_pair_grad(as_rows(P[a]), as_rows(P[b]), list(theta[0][a]), list(theta[0][b]), intr[a],
+                                intr[b], grid, lazy, a, b, params)
+        got = pg[pair_index(a, b, g.n_views)]
+        err = np.linalg.norm(got - gref) / (np.linalg.norm(gref) + 1e-30)
+        assert err <= 2e-3, (a, b, err)
+    # central differences of the GPU cost, h = 1e-3 deg / mm
+    h = 1e-3
+    idx = [(v, q) for v in rng.choice(g.n_views, 6, replace=False).tolist() for q in range(6)]
+    th = np.repeat(theta, 2 * len(idx), axis=0)
+    for i, (v, q) in enumerate(idx):
+        th[2 * i, v, q] += h
+        th[2 * i + 1, v, q] -= h
+    c = scan.cost(th, w.K, w.R_mm, geom="f64").cpu().numpy()
+    fd = (c[0::2] - c[1::2]) / (2 * h)
+    an = np.array([grad[v, q] for v, q in idx])
+    err = np.linalg.norm(fd - an) / np.linalg.norm(fd)
+    _say(f"  adj248 FD rel L2 {err:.2e}")
+    assert err <= 3e-2
+    scan.free()
+    del imgs
+    torch.cuda.empty_cache()
+
+
+def test_autograd_function(eng, small16):
+    import torch
+
+    from paper_1806_02637_amd.autograd import ecc_cost
+
+    _say("case: torch.autograd.Function")
+    s = small16
+    g = s["geom"]
+    scan = eng.load_scan(s["P"], s["intr"], s["images"])
+    scan.build_sinograms(s["w"].n_alpha, s["w"].n_t, s["w"].ds_px, "f32")
+    th = torch.tensor(inputs.random_motion(3, 2, g.n_views), device="cuda", requires_grad=True)
+    cost = ecc_cost(th, scan, s["w"].K, s["w"].R_mm)
+    loss = (cost * torch.tensor([2.0, -0.5], device="cuda", dtype=torch.float64)).sum()
+    loss.backward()
+    _, grad = scan.cost_grad(th.detach(), s["w"].K, s["w"].R_mm)
+    ref = grad.double() * torch.tensor([2.0, -0.5], device="cuda", dtype=torch.float64)[:, None, None]
+    assert torch.allclose(th.grad, ref)
+    with torch.no_grad():
+        c2 = ecc_cost(th, scan, s["w"].K, s["w"].R_mm)
+    assert torch.equal(c2, cost.detach())
+    scan.free()

@@ -1,0 +1,139 @@
+"""Precision forms against the FP64 oracle: BF16 / FP16 sinogram storage
+(FP32 arithmetic) and FP64 per-plane geometry.
+
+Error model for storage rounding (unit roundoff u: 2^-8 BF16, 2^-11 FP16,
+round to nearest even): each tap carries noise of variance <= u^2 S^2 / 3, so
+the pairwise mean of squared differences is biased upwards by about
+(2 u^2 / 3) * mean((S_a^2 + S_b^2) / 2), i.e. a relative error of about
+(2 u^2 / 3) / nu with nu = d / mean(S^2) the normalised inconsistency, plus a
+zero-mean term of order 2 u sqrt(nu / N).  The bound asserted per hypothesis
+is 4x that model (computed from the oracle's own S values) plus the FP32 bar
+of 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.ecc import as_rows, lookup, pair_geometry, pair_index, pair_list
+from paper_1806_02637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+
+    from paper_1806_02637_amd import engine
+
+    assert torch.cuda.is_available()
+    e = engine.Engine(0)
+    yield e
+    e.close()
+
+
+def _model_bound(P, intr, theta, grid, sino, params, u, pairs=None):
+    """Per-hypothesis relative error bound of the storage-rounding model."""
+    bias = 0.0
+    noise2 = 0.0
+    total = 0.0
+    for a, b in pairs or pair_list(len(P)):
+        g = pair_geometry(as_rows(P[a]), as_rows(P[b]), list(theta[a]), list(theta[b]), params)
+        Sa, ha = lookup(g["l_a"], intr[a], grid, sino, a)
+        Sb, hb = lookup(g["l_b"], intr[b], grid, sino, b)
+        h = ha & hb
+        if not h.any():
+            continue
+        ms = np.mean(0.5 * (Sa[h] ** 2 + Sb[h] ** 2))
+        d = np.mean((Sa[h] - Sb[h]) ** 2)
+        total += d
+        bias += (2 * u * u / 3) * ms
+        noise2 += (2 * u) ** 2 * d * ms / h.sum()
+    return (bias + math.sqrt(noise2)) / total
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_storage_precision_small16(eng, small16, dtype):
+    _say(f"case: storage {dtype} small16 vs oracle")
+    s = small16
+    g = s["geom"]
+    scan = eng.load_scan(s["P"], s["intr"], s["images"])
+    scan.build_sinograms(s["w"].n_alpha, s["w"].n_t, s["w"].ds_px, dtype)
+    thetas = inputs.random_motion(1001, 3, g.n_views)
+    cost = scan.cost(thetas, s["params"].K, s["params"].R_mm).cpu().numpy()
+    for h in range(3):
+        c_ref = oracle.ecc_cost(s["P"], s["intr"], thetas[h], s["grid"], s["sino"], s["params"])[0]
+        rel = abs(cost[h] - c_ref) / c_ref
+        bound = 4 * _model_bound(s["P"], s["intr"], thetas[h], s["grid"], s["sino"], s["params"], U[dtype]) + 1e-5
+        _say(f"  {dtype} hyp {h}: rel err {rel:.2e} (bound {bound:.2e})")
+        assert rel <= bound
+    # decoded storage equals the FP32 sinogram rounded to the storage type
+    got = scan.read_sinogram(5)
+    ref = s["sino"].data[5]
+    assert np.abs(got - ref).max() <= 1.01 * U[dtype] * np.abs(ref).max()
+    scan.free()
+
+
+def test_variants_full496_sampled(eng):
+    """The 496-view workload in the benchmark's configuration (B = 32,
+    K = 512): FP32, BF16 and FP16 storage and FP64 plane geometry, each on
+    sampled (hypothesis, pair) values against the oracle."""
+    import torch
+
+    _say("case: precision variants full496 sampled")
+    w = inputs.WORKLOADS["full496"]
+    g = w.geom
+    P, intr = g.projection_matrices(), g.intrinsics()
+    imgs = inputs.project(g, w.phantom(), device="cuda", as_tensor=True)
+    thetas = w.motion()
+    rng = np.random.default_rng(31)
+    sel = []
+    while len(sel) < 6:
+        a, b = sorted(rng.choice(g.n_views, 2, replace=False).tolist())
+        if b - a < 40:  # favour the short baselines the FP64 geometry is for
+            sel.append((a, b))
+    views = sorted({v for ab in sel for v in ab})
+    host = {v: imgs[v].cpu().numpy() for v in views}
+
+    class Imgs:
+        def __getitem__(self, v):
+            return host[v]
+
+    grid = oracle.SinoGrid(g.W, g.H, w.n_alpha, w.n_t, w.ds_px)
+    lazy = oracle.LazySinograms(Imgs(), grid, intr)
+    params = oracle.EccParams(w.K, w.R_mm)
+    hyps = (0, 17)
+    ref = {}
+    for a, b in sel:
+        for h in hyps:
+            e, _, _ = oracle.ecc_pair(as_rows(P[a]), as_rows(P[b]), list(thetas[h][a]), list(thetas[h][b]), intr[a],
+                                      intr[b], grid, lazy, a, b, params)
+            ref[(a, b, h)] = float(e)
+    for dtype, geom, tol in (("f32", "f32", None), ("f32", "f64", None), ("bf16", "f32", "bf16"),
+                             ("f16", "f32", "f16")):
+        scan = eng.load_scan(P, intr, imgs)
+        scan.build_sinograms(w.n_alpha, w.n_t, w.ds_px, dtype)
+        _, pairs = scan.cost(thetas, w.K, w.R_mm, geom=geom, with_pairs=True)
+        pairs = pairs.cpu().numpy()
+        errs = []
+        for (a, b, h), e_ref in ref.items():
+            got = pairs[h, pair_index(a, b, g.n_views)]
+            rel = abs(got - e_ref) / e_ref
+            errs.append(rel)
+            if tol is None:
+                assert rel <= 2e-4, (dtype, geom, a, b, h, rel)
+            else:
+                bnd = 4 * _model_bound(P, intr, thetas[h], grid, lazy, params, U[tol], [(a, b)]) + 2e-4
+                assert rel <= bnd, (dtype, a, b, h, rel, bnd)
+        _say(f"  {dtype}/{geom}: sampled pair rel err median {np.median(errs):.2e} max {np.max(errs):.2e}")
+        scan.free()
+    del imgs
+    torch.cuda.empty_cache()

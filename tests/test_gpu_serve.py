@@ -1,0 +1,153 @@
+"""Served form: continuous batching over several resident scans of uneven
+size, admission by HBM arena, overlap on the device, and results that are
+identical (bitwise) alone and in the mix."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_1806_02637_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def served():
+    import torch
+
+    from paper_1806_02637_amd import engine
+
+    assert torch.cuda.is_available()
+    eng = engine.Engine(0)
+    specs = [(13, 96, 80, 3.0, 90, 97, 64), (24, 160, 128, 2.0, 120, 151, 128), (40, 256, 192, 1.4, 180, 241, 128)]
+    scans = []
+    for i, (n, W, H, pitch, na, nt, K) in enumerate(specs):
+        g = inputs.ScanGeometry(n, W, H, pitch)
+        imgs = inputs.project(g, inputs.random_phantom(50 + i, 12), device="cuda", as_tensor=True)
+        sc = eng.load_scan(g.projection_matrices(), g.intrinsics(), imgs)
+        sc.build_sinograms(na, nt, 0.5, "bf16")
+        scans.append((sc, g, K, g.default_object_radius()))
+    yield eng, scans
+    for sc, *_ in scans:
+        sc.free()
+    eng.close()
+
+
+def _trace(scans, n, rate, seed, B=8):
+    from paper_1806_02637_amd.serve import poisson_arrivals
+
+    rng = np.random.default_rng(seed)
+    arr = poisson_arrivals(rate, n, seed)
+    out = []
+    for i in range(n):
+        sc, g, K, R = scans[int(rng.integers(len(scans)))]
+        th = inputs.random_motion(int(rng.integers(1 << 30)), B, g.n_views)
+        out.append((float(arr[i]), sc, th, K, R, bool(rng.integers(2))))
+    return out
+
+
+def test_alone_equals_mix(served):
+    from paper_1806_02637_amd.serve import Server, latency_summary, replay
+
+    _say("case: serve alone vs mix")
+    eng, scans = served
+    trace = _trace(scans, 40, rate=2000.0, seed=3)
+    # alone: the direct API, one request at a time
+    alone = []
+    for _, sc, th, K, R, g in trace:
+        if g:
+            c, gr = sc.cost_grad(th, K, R)
+            alone.append((c.cpu().numpy(), gr.cpu().numpy()))
+        else:
+            alone.append((sc.cost(th, K, R).cpu().numpy(), None))
+    srv = Server(eng, n_slots=4, arena_bytes=1 << 30)
+    results, makespan = replay(srv, trace)
+    for (c0, g0), r in zip(alone, results):
+        assert np.array_equal(r.cost, c0)
+        if g0 is not None:
+            assert np.array_equal(r.grad, g0)
+    lat = latency_summary(results)
+    _say(f"  40 requests in {makespan * 1e3:.1f} ms, p50 {lat['p50_ms']:.2f} ms, p99 {lat['p99_ms']:.2f} ms")
+    assert {r.slot for r in results} >= {0, 1}  # more than one slot used
+    srv.close()
+
+
+def test_arena_budget_admission(served):
+    from paper_1806_02637_amd.serve import Server
+
+    _say("case: serve arena admission")
+    eng, scans = served
+    sc, g, K, R = scans[2]
+    probe = Server(eng, n_slots=4, arena_bytes=1 << 30)
+    need = probe.request_bytes(sc, 8, True)
+    probe.close()
+    # an arena that holds exactly one such request: at most one runs at a time
+    srv = Server(eng, n_slots=4, arena_bytes=need + 1024)
+    th = inputs.random_motion(9, 8, g.n_views)
+    t_sub, ids = [], []
+    for _ in range(6):
+        t_sub.append(time.perf_counter())
+        ids.append(srv.submit(sc, th, K, R, with_grad=True))
+    res = [srv.wait(i) for i in ids]
+    iv = sorted((t + r.queue_ms * 1e-3, t + r.total_ms * 1e-3) for t, r in zip(t_sub, res))
+    for (a0, a1), (b0, b1) in zip(iv[:-1], iv[1:]):
+        assert b0 >= a1 - 2e-4  # admitted only after the previous one finished
+    for r in res[1:]:
+        assert np.array_equal(r.cost, res[0].cost)
+    # a request bigger than the whole arena fails cleanly
+    big = inputs.random_motion(10, 64, g.n_views)
+    rid = srv.submit(sc, big, K, R, with_grad=True)
+    with pytest.raises(binding.EccError) as ei:
+        srv.wait(rid)
+    assert ei.value.status == binding.ECC_E_BUDGET
+    srv.close()
+
+
+def test_concurrent_requests_overlap(served):
+    from paper_1806_02637_amd.serve import Server
+
+    _say("case: serve overlap")
+    eng, scans = served
+    sc, g, K, R = scans[2]
+    srv = Server(eng, n_slots=4, arena_bytes=1 << 30)
+    th = inputs.random_motion(11, 32, g.n_views)
+    t_sub, ids = [], []
+    for _ in range(8):
+        t_sub.append(time.perf_counter())
+        ids.append(srv.submit(sc, th, K, R))
+    res = [srv.wait(i) for i in ids]
+    iv = [(t + r.queue_ms * 1e-3, t + r.total_ms * 1e-3) for t, r in zip(t_sub, res)]
+    overlap = max(sum(1 for a, b in iv if a <= x < b) for x, _ in iv)
+    assert overlap >= 2
+    srv.close()
+
+
+def test_freed_scan_fails_queued_requests(served):
+    from paper_1806_02637_amd.serve import Server
+
+    _say("case: serve freed scan")
+    eng, scans = served
+    g = inputs.ScanGeometry(10, 64, 64, 4.0)
+    imgs = inputs.project(g, inputs.random_phantom(77, 5))
+    sc = eng.load_scan(g.projection_matrices(), g.intrinsics(), imgs)
+    sc.build_sinograms(60, 65, 0.5, "f32")
+    srv = Server(eng, n_slots=1, arena_bytes=64 << 20)
+    th = inputs.random_motion(12, 4, g.n_views)
+    R = g.default_object_radius()
+    ids = [srv.submit(sc, th, 64, R) for _ in range(30)]
+    sc.free()
+    ok = failed = 0
+    for rid in ids:
+        try:
+            srv.wait(rid)
+            ok += 1
+        except binding.EccError as e:
+            assert e.status == binding.ECC_E_NOSCAN
+            failed += 1
+    assert ok + failed == 30 and failed >= 1
+    srv.close()
