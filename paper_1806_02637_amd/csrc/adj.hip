@@ -1,21 +1,20 @@
 // Adjoint of the consistency cost: d cost / d theta for every view's six
 // motion parameters, with the line geometry recomputed rather than stored.
 //
-// ecc_adj      same work split as the forward kernel (4 hypotheses x one
-//              64-pair tile per workgroup).  Per pair:
-//                1. forward sweep over the K planes -> d, N (Eq. 15), e (Eq. 16);
-//                2. reverse sweep over the planes: dE/dS_a = +g, dE/dS_b = -g with
-//                   g = de/dd * 2 (S_a - S_b) / N on planes hitting both
-//                   detectors; through the weighted bilinear lookup to
-//                   (alpha, t), through atan2 / offset to the line l, through
-//                   l = H (cos k, sin k) to the 6 + 6 line-map entries and to
-//                   kappa_max (k = kappa_max ((2k+1)/K - 1)); wave-shuffle sum
-//                   of those 13 sensitivities, kept by lane (pair % 64);
-//              then every lane owns one pair and runs 12 FP64 forward-mode
-//              (dual number) sweeps of the per-pair geometry -- one per motion
-//              parameter of views a and b, seeded with dP'/dtheta -- and
-//              contracts them with the 13 sensitivities.
-// reduce_grad  fixed-order sum of the per-pair 12-vectors into grad[B][N][6].
+// ecc_adj       same work split as the forward kernel (4 hypotheses x one
+//               pair tile per workgroup).  Per pair:
+//                 1. forward sweep over the K planes -> d, N (Eq. 15), e (Eq. 16);
+//                 2. reverse sweep over the planes: dE/dS_a = +g, dE/dS_b = -g with
+//                    g = de/dd * 2 (S_a - S_b) / N on planes hitting both
+//                    detectors; through the weighted bilinear lookup to
+//                    (alpha, t), through atan2 / offset to the line l, through
+//                    l = H (cos k, sin k) to the 6 + 6 line-map entries and to
+//                    kappa_max (k = kappa_max ((2k+1)/K - 1)); fixed-order wave
+//                    sums of those 13 sensitivities, written per pair.
+// pair_tangent  one thread per (hypothesis, pair, motion parameter): an FP64
+//               forward-mode (dual number) sweep of the pair's geometry seeded
+//               with dP'/dtheta, contracted with the 13 sensitivities.
+// reduce_grad   fixed-order sum of the per-pair 12-vectors into grad[B][N][6].
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -30,10 +29,9 @@ namespace ecc {
 // Reverse sweep through one view's lookup: accumulates dE/dH (6) and the
 // plane-angle derivative dE/dkappa_k given gS = dE/dS.
 template <class Tap, class G>
-__device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const Tap *sview, const EvalConsts &ec,
+__device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const Taps &tp, const EvalConsts &ec,
                                                float inv_f2, float scale, float gS, const LineCoord<G> &c,
                                                float gH[6], float &gk) {
-    const Taps tp = Tap::load(sview + (uint32_t)(c.m * ec.row_elems + c.k + 1));
     const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
     const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
     const float Bv = fmaf(c.fa, r1 - r0, r0);
@@ -102,10 +100,8 @@ __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const View
 
 template <class Tap, class G>
 __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ sino,
-                                                      const PairConst<G> *__restrict__ table,
-                                                      const ViewGeom *__restrict__ vt,
-                                                      const ViewGeomGrad *__restrict__ vg, EvalConsts ec,
-                                                      float *__restrict__ pair_grad, double *__restrict__ partials,
+                                                      const PairConst<G> *__restrict__ table, EvalConsts ec,
+                                                      float *__restrict__ sens, double *__restrict__ partials,
                                                       int n_tiles) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -116,20 +112,18 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
     const int tile = (int)(w / hyp_groups);
     const int hyp = (int)(w % hyp_groups) * kWavesPerBlock + wave;
     if (hyp >= ec.B) return;  // no barriers in this kernel
-    const ViewGeom *vth = vt + (int64_t)hyp * ec.n_views;
-    const PairConst<G> *tab = table + (int64_t)hyp * ec.n_pairs;
+    __shared__ PairConst<G> slots[kWavesPerBlock][kPairsPerWave];
+    stage_tile(slots[wave], table + (int64_t)hyp * ec.n_pairs, tile, lane, ec.n_views);
 
     const Tap *base = (const Tap *)sino;
-    const float kscale = 2.0f / (float)ec.K;
+    const float kinv = 1.0f / (float)ec.K;
     double wave_acc = 0.0;
-    float mine[13];
-    for (int i = 0; i < 13; ++i) mine[i] = 0.0f;
     for (int q = 0; q < kPairsPerWave; ++q) {
-        int qa, qb;
-        if (!tile_pair(tile, q, ec.n_views, qa, qb)) continue;
-        const PairConst<G> pc = tab[pair_index(qa, qb, ec.n_views)];
-        const Tap *sa = base + (int64_t)qa * ec.view_elems;
-        const Tap *sb = base + (int64_t)qb * ec.view_elems;
+        const PairConst<G> pc = uniform(slots[wave][q]);
+        if (pc.va < 0) continue;
+        const int64_t p = pair_index(pc.va, pc.vb, ec.n_views);
+        const Tap *sa = base + (int64_t)pc.va * ec.view_elems;
+        const Tap *sb = base + (int64_t)pc.vb * ec.view_elems;
         // 1. forward sweep
         float acc = 0.0f;
         int cnt = 0;
@@ -166,14 +160,16 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                 const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
                 const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
                 if (ca.hit && cb.hit) {
-                    const float Sa = sample_at<Tap, G>(ca, sa, ec, pc.inv_f2a, pc.sa);
-                    const float Sb = sample_at<Tap, G>(cb, sb, ec, pc.inv_f2b, pc.sb);
+                    const Taps ta = load_taps<Tap, G>(ca, sa, ec);
+                    const Taps tb = load_taps<Tap, G>(cb, sb, ec);
+                    const float Sa = sample_taps<Tap, G>(ca, ta, pc.inv_f2a, pc.sa);
+                    const float Sb = sample_taps<Tap, G>(cb, tb, pc.inv_f2b, pc.sb);
                     const float gS = coef * (Sa - Sb);
                     float gk = 0.0f;
-                    lookup_adjoint<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, gS, ca, g, gk);
-                    lookup_adjoint<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, -gS, cb, g + 6, gk);
+                    lookup_adjoint<Tap, G>(pc.ha, cs, sn, ta, ec, pc.inv_f2a, pc.sa, gS, ca, g, gk);
+                    lookup_adjoint<Tap, G>(pc.hb, cs, sn, tb, ec, pc.inv_f2b, pc.sb, -gS, cb, g + 6, gk);
                     // kappa_k = kappa_max ((2k + 1) / K - 1)
-                    g[12] = fmaf(gk, (float)(2 * k + 1) * (0.5f * kscale) - 1.0f, g[12]);
+                    g[12] = fmaf(gk, (float)(2 * k + 1) * kinv - 1.0f, g[12]);
                 }
                 const G c2 = cs * pc.rc - sn * pc.rs;
                 sn = sn * pc.rc + cs * pc.rs;
@@ -181,44 +177,60 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
             }
             for (int i = 0; i < 13; ++i) g[i] = wave_sum(g[i]);
         }
-        if (lane == q)
-            for (int i = 0; i < 13; ++i) mine[i] = g[i];
+        if (lane == 0) {
+            float *out = sens + ((int64_t)hyp * ec.n_pairs + p) * 13;
+            for (int i = 0; i < 13; ++i) out[i] = g[i];
+        }
     }
     if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
+}
 
-    // 3. per-pair tangent sweeps, one pair per lane
-    int my_a, my_b;
-    if (tile_pair(tile, lane, ec.n_views, my_a, my_b)) {
-        const int64_t gi = (int64_t)my_a + (int64_t)hyp * ec.n_views;
-        const int64_t gj = (int64_t)my_b + (int64_t)hyp * ec.n_views;
-        float *out = pair_grad + ((int64_t)hyp * ec.n_pairs + pair_index(my_a, my_b, ec.n_views)) * 12;
-        for (int dir = 0; dir < 12; ++dir)
-            out[dir] = (float)pair_tangent(vth[my_a], vth[my_b], vg[gi], vg[gj], dir, ec.R_mm, mine);
-    }
+__global__ __launch_bounds__(256) void pair_tangent_kernel(const ViewGeom *__restrict__ vt,
+                                                           const ViewGeomGrad *__restrict__ vg,
+                                                           const float *__restrict__ sens, EvalConsts ec,
+                                                           float *__restrict__ pair_grad) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)ec.B * ec.n_pairs * 12) return;
+    const int dir = (int)(idx % 12);
+    const int64_t hp = idx / 12;  // hyp * n_pairs + pair
+    const int hyp = (int)(hp / ec.n_pairs);
+    int a, b;
+    pair_from_index(hp % ec.n_pairs, ec.n_views, a, b);
+    const int64_t ga = (int64_t)hyp * ec.n_views + a, gb = (int64_t)hyp * ec.n_views + b;
+    float g13[13];
+    for (int i = 0; i < 13; ++i) g13[i] = sens[hp * 13 + i];
+    pair_grad[hp * 12 + dir] = (float)pair_tangent(vt[ga], vt[gb], vg[ga], vg[gb], dir, ec.R_mm, g13);
 }
 
 template <class Tap, class G>
-static hipError_t launch_adj_t(const void *sino, const void *table, const ViewGeom *vt, const ViewGeomGrad *vg,
-                               EvalConsts ec, float *pair_grad, double *partials, int n_tiles, hipStream_t s) {
+static hipError_t launch_adj_t(const void *sino, const void *table, EvalConsts ec, float *sens, double *partials,
+                               int n_tiles, hipStream_t s) {
     const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
     const int64_t blocks = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL((ecc_adj_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                       occupancy_lds_bytes(), s, sino,
-                       (const PairConst<G> *)table, vt, vg, ec, pair_grad, partials, n_tiles);
+                       occupancy_lds_bytes(sizeof(PairConst<G>) * kPairsPerWave * kWavesPerBlock), s, sino,
+                       (const PairConst<G> *)table, ec, sens, partials, n_tiles);
     return hipGetLastError();
 }
 
 hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *vt, const ViewGeomGrad *vg,
-                          EvalConsts ec, int dtype, float *pair_grad, double *partials, int n_tiles,
+                          EvalConsts ec, int dtype, float *sens, float *pair_grad, double *partials, int n_tiles,
                           hipStream_t s) {
+    hipError_t e;
     if (ec.geom64) {
-        if (dtype == 0) return launch_adj_t<TapF32, double>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
-        if (dtype == 1) return launch_adj_t<TapBF16, double>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
-        return launch_adj_t<TapF16, double>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
+        if (dtype == 0) e = launch_adj_t<TapF32, double>(sino, table, ec, sens, partials, n_tiles, s);
+        else if (dtype == 1) e = launch_adj_t<TapBF16, double>(sino, table, ec, sens, partials, n_tiles, s);
+        else e = launch_adj_t<TapF16, double>(sino, table, ec, sens, partials, n_tiles, s);
+    } else {
+        if (dtype == 0) e = launch_adj_t<TapF32, float>(sino, table, ec, sens, partials, n_tiles, s);
+        else if (dtype == 1) e = launch_adj_t<TapBF16, float>(sino, table, ec, sens, partials, n_tiles, s);
+        else e = launch_adj_t<TapF16, float>(sino, table, ec, sens, partials, n_tiles, s);
     }
-    if (dtype == 0) return launch_adj_t<TapF32, float>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
-    if (dtype == 1) return launch_adj_t<TapBF16, float>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
-    return launch_adj_t<TapF16, float>(sino, table, vt, vg, ec, pair_grad, partials, n_tiles, s);
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)ec.B * ec.n_pairs * 12;
+    hipLaunchKernelGGL(pair_tangent_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vt, vg, sens, ec,
+                       pair_grad);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -138,8 +138,10 @@ hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalCo
 }
 
 // A wave = one hypothesis x one pair tile; a workgroup = 4 hypotheses of the
-// same tile (they read nearly the same sinogram cells).
-template <class Tap, class G>
+// same tile (they read nearly the same sinogram cells).  UNROLL2 walks two
+// planes per iteration (two independent gather chains); UNIFORM moves the
+// pair constants from LDS into scalar registers.
+template <class Tap, class G, bool UNROLL2, bool UNIFORM>
 __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ sino,
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
                                                       float *__restrict__ out_pair, double *__restrict__ partials,
@@ -153,30 +155,54 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     const int tile = (int)(w / hyp_groups);
     const int hyp = (int)(w % hyp_groups) * kWavesPerBlock + wave;
     if (hyp >= ec.B) return;  // no barriers in this kernel
-    const PairConst<G> *tab = table + (int64_t)hyp * ec.n_pairs;
+    __shared__ PairConst<G> slots[kWavesPerBlock][kPairsPerWave];
+    stage_tile(slots[wave], table + (int64_t)hyp * ec.n_pairs, tile, lane, ec.n_views);
 
     const Tap *base = (const Tap *)sino;
     double wave_acc = 0.0;
     for (int q = 0; q < kPairsPerWave; ++q) {
-        int a, b;
-        if (!tile_pair(tile, q, ec.n_views, a, b)) continue;
+        const PairConst<G> pc = UNIFORM ? uniform(slots[wave][q]) : slots[wave][q];
+        const int a = pc.va, b = pc.vb;
+        if (a < 0) continue;
         const int64_t p = pair_index(a, b, ec.n_views);
-        const PairConst<G> pc = tab[p];
         const Tap *sa = base + (int64_t)a * ec.view_elems;
         const Tap *sb = base + (int64_t)b * ec.view_elems;
         float acc = 0.0f;
         int cnt = 0;
         // plane angle of this lane, advanced by one wave step (64 dk) per
-        // iteration through the rotation (rc, rs)
+        // plane through the rotation (rc, rs)
         G sn, cs;
         g_sincos(pc.k0 + (G)lane * pc.dk, &sn, &cs);
-        for (int k = lane; k < ec.K; k += 64) {
-            bool hit_a, hit_b;
-            const float Sa = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, hit_a);
-            const float Sb = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hit_b);
-            if (hit_a && hit_b) {
-                const float diff = Sa - Sb;
-                acc = fmaf(diff, diff, acc);
+        int k = lane;
+        if (UNROLL2) {
+            for (; k + 64 < ec.K; k += 128) {
+                const G cs2 = cs * pc.rc - sn * pc.rs;
+                const G sn2 = sn * pc.rc + cs * pc.rs;
+                bool ha0, hb0, ha1, hb1;
+                const float Sa0 = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, ha0);
+                const float Sb0 = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hb0);
+                const float Sa1 = lookup<Tap, G>(pc.ha, cs2, sn2, sa, ec, pc.inv_f2a, pc.sa, ha1);
+                const float Sb1 = lookup<Tap, G>(pc.hb, cs2, sn2, sb, ec, pc.inv_f2b, pc.sb, hb1);
+                const float d0 = Sa0 - Sb0, d1 = Sa1 - Sb1;
+                if (ha0 && hb0) {
+                    acc = fmaf(d0, d0, acc);
+                    ++cnt;
+                }
+                if (ha1 && hb1) {
+                    acc = fmaf(d1, d1, acc);
+                    ++cnt;
+                }
+                cs = cs2 * pc.rc - sn2 * pc.rs;
+                sn = sn2 * pc.rc + cs2 * pc.rs;
+            }
+        }
+        for (; k < ec.K; k += 64) {
+            bool ha0, hb0;
+            const float Sa0 = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, ha0);
+            const float Sb0 = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hb0);
+            if (ha0 && hb0) {
+                const float d0 = Sa0 - Sb0;
+                acc = fmaf(d0, d0, acc);
                 ++cnt;
             }
             const G c2 = cs * pc.rc - sn * pc.rs;
@@ -206,30 +232,53 @@ static int blocks_per_cu_cap() {
     return cap;
 }
 
-size_t occupancy_lds_bytes() {
+size_t occupancy_lds_bytes(size_t static_bytes) {
     const int cap = blocks_per_cu_cap();
     if (cap <= 0) return 0;
     size_t b = (160u * 1024u) / (size_t)cap;
     b = (b / 1024) * 1024;
-    return b > 65536 ? 65536 : b;
+    if (b > 65536) b = 65536;
+    return b > static_bytes ? b - static_bytes : 0;
+}
+
+template <class Tap, class G, bool UNROLL2, bool UNIFORM>
+static hipError_t launch_fwd_v(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
+                               int n_tiles, hipStream_t s) {
+    const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
+    const int64_t blocks = 8 * ((total + 7) / 8);
+    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G, UNROLL2, UNIFORM>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
+                       occupancy_lds_bytes(sizeof(PairConst<G>) * kPairsPerWave * kWavesPerBlock), s, sino,
+                       (const PairConst<G> *)table, ec, out_pair, partials, n_tiles);
+    return hipGetLastError();
+}
+
+// Plane-loop variant of the FP32 path (bit 0: two planes per iteration,
+// bit 1: pair constants in scalar registers); ECC_FWD_VARIANT overrides.
+static int fwd_variant() {
+    static int v = [] {
+        const char *e = getenv("ECC_FWD_VARIANT");
+        return e ? atoi(e) & 3 : kDefaultFwdVariant;
+    }();
+    return v;
 }
 
 template <class Tap, class G>
 static hipError_t launch_fwd_t(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
                                int n_tiles, hipStream_t s) {
-    const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
-    const int64_t blocks = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                       occupancy_lds_bytes(), s, sino, (const PairConst<G> *)table, ec, out_pair, partials, n_tiles);
-    return hipGetLastError();
+    switch (fwd_variant()) {
+        case 1: return launch_fwd_v<Tap, G, true, false>(sino, table, ec, out_pair, partials, n_tiles, s);
+        case 2: return launch_fwd_v<Tap, G, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
+        case 3: return launch_fwd_v<Tap, G, true, true>(sino, table, ec, out_pair, partials, n_tiles, s);
+        default: return launch_fwd_v<Tap, G, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
+    }
 }
 
 hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
                           double *partials, int n_tiles, hipStream_t s) {
     if (ec.geom64) {
-        if (dtype == 0) return launch_fwd_t<TapF32, double>(sino, table, ec, out_pair, partials, n_tiles, s);
-        if (dtype == 1) return launch_fwd_t<TapBF16, double>(sino, table, ec, out_pair, partials, n_tiles, s);
-        return launch_fwd_t<TapF16, double>(sino, table, ec, out_pair, partials, n_tiles, s);
+        if (dtype == 0) return launch_fwd_v<TapF32, double, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
+        if (dtype == 1) return launch_fwd_v<TapBF16, double, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
+        return launch_fwd_v<TapF16, double, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
     }
     if (dtype == 0) return launch_fwd_t<TapF32, float>(sino, table, ec, out_pair, partials, n_tiles, s);
     if (dtype == 1) return launch_fwd_t<TapBF16, float>(sino, table, ec, out_pair, partials, n_tiles, s);

@@ -89,8 +89,10 @@ size_t pair_const_bytes(bool geom64);
 hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s);
 hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
                           double *partials, int n_tiles, hipStream_t s);
+// adjoint: plane kernel -> per-pair sensitivities sens [B][n_pairs][13], then
+// per-pair tangent sweeps -> pair_grad [B][n_pairs][12]
 hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *vt, const ViewGeomGrad *vg,
-                          EvalConsts ec, int dtype, float *pair_grad, double *partials, int n_tiles,
+                          EvalConsts ec, int dtype, float *sens, float *pair_grad, double *partials, int n_tiles,
                           hipStream_t s);
 hipError_t launch_reduce_cost(const double *partials, int n_tiles, int B, double *out_cost, hipStream_t s);
 hipError_t launch_reduce_grad(const float *pair_grad, int B, int n_views, float *grad, hipStream_t s);
@@ -105,6 +107,9 @@ constexpr int kImgPad = 3;
 constexpr int kWavesPerBlock = 4;
 // default cap on resident plane-kernel workgroups per CU (0 = no cap)
 constexpr int kDefaultBlocksPerCU = 4;
-size_t occupancy_lds_bytes();
+// default plane-loop variant of the FP32 forward kernel (see ecc.hip)
+constexpr int kDefaultFwdVariant = 2;
+// dynamic LDS that, added to a kernel's static LDS, enforces the cap
+size_t occupancy_lds_bytes(size_t static_bytes);
 
 }  // namespace ecc

@@ -116,7 +116,7 @@ int n_tiles_for(int n_views) {
 
 // Workspace layout of an evaluation.
 struct Workspace {
-    uint64_t vt_off, vg_off, table_off, part_off, pgrad_off, total;
+    uint64_t vt_off, vg_off, table_off, part_off, sens_off, pgrad_off, total;
 };
 
 Workspace workspace_layout(const Scan *s, int B, bool grad) {
@@ -131,6 +131,8 @@ Workspace workspace_layout(const Scan *s, int B, bool grad) {
     off += align256(pair_const_bytes(true) * (uint64_t)B * n_pairs);
     w.part_off = off;
     off += align256(sizeof(double) * (uint64_t)B * n_tiles_for(s->n_views));
+    w.sens_off = off;
+    if (grad) off += align256(sizeof(float) * 13ull * (uint64_t)B * n_pairs);
     w.pgrad_off = off;
     if (grad) off += align256(sizeof(float) * 12ull * (uint64_t)B * n_pairs);
     w.total = off;
@@ -505,7 +507,8 @@ ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double 
     void *table = ws + w.table_off;
     HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, vg, hs));
     HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs));
-    HIP_TRY(launch_ecc_adj(s->sino_dev, table, vt, vg, ec, s->layout.dtype, pgrad, partials, n_tiles, hs));
+    float *sens = (float *)(ws + w.sens_off);
+    HIP_TRY(launch_ecc_adj(s->sino_dev, table, vt, vg, ec, s->layout.dtype, sens, pgrad, partials, n_tiles, hs));
     HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
     HIP_TRY(launch_reduce_grad(pgrad, B, s->n_views, grad_dev, hs));
     return ok();

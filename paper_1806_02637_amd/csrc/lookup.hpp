@@ -27,6 +27,36 @@ struct PairConst {
     int va, vb;
 };
 
+// Wave-uniform copy of a pair's constants (read from LDS by every lane) into
+// scalar registers.
+__device__ __forceinline__ float uniform(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uniform(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <class G>
+__device__ __forceinline__ PairConst<G> uniform(const PairConst<G> &p) {
+    PairConst<G> u;
+    for (int i = 0; i < 6; ++i) {
+        u.ha[i] = uniform(p.ha[i]);
+        u.hb[i] = uniform(p.hb[i]);
+    }
+    u.k0 = uniform(p.k0);
+    u.dk = uniform(p.dk);
+    u.rc = uniform(p.rc);
+    u.rs = uniform(p.rs);
+    u.inv_f2a = uniform(p.inv_f2a);
+    u.inv_f2b = uniform(p.inv_f2b);
+    u.sa = uniform(p.sa);
+    u.sb = uniform(p.sb);
+    u.va = uniform(p.va);
+    u.vb = uniform(p.vb);
+    return u;
+}
+
 // ---- storage types: one load returns the four taps of a bilinear cell ----
 struct Taps {
     float s00, s10, s01, s11;  // S[m][k], S[m+1][k], S[m][k+1], S[m+1][k+1]
@@ -36,6 +66,7 @@ typedef float f32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
 struct TapF32 {
+    static constexpr bool kScaled = false;
     float lo, hi;
     static __device__ __forceinline__ Taps load(const TapF32 *p) {
         const f32x4_a8 v = *(const f32x4_a8 *)p;
@@ -44,6 +75,7 @@ struct TapF32 {
 };
 
 struct TapBF16 {
+    static constexpr bool kScaled = false;
     uint32_t bits;
     static __device__ __forceinline__ Taps load(const TapBF16 *p) {
         const u32x2_a4 v = *(const u32x2_a4 *)p;
@@ -53,6 +85,7 @@ struct TapBF16 {
 };
 
 struct TapF16 {
+    static constexpr bool kScaled = true;  // per-view power-of-two storage scale
     uint32_t bits;
     static __device__ __forceinline__ float h2f(uint32_t h) {
         return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
@@ -67,7 +100,8 @@ struct TapF16 {
 // FP32: fitted polynomials (poly_coeffs.hpp) -- the plane angle only selects
 // which plane of the pencil is sampled, identically for both views, and the
 // line angle enters the lookup through an FP32 fraction anyway.  FP64: the
-// library functions.
+// library sincos (once per lane and pair), a 16-term fitted atan (2e-14 rad)
+// and a Newton-refined reciprocal square root.
 __device__ __forceinline__ void g_sincos(float x, float *s, float *c) {
     // |x| <= pi/2 (plane angles of the pencil)
     const float x2 = x * x;
@@ -94,9 +128,26 @@ __device__ __forceinline__ float g_atan2_upper(float y, float x) {
     a = y > ax ? 1.57079632679489662f - a : a;
     return x < 0.0f ? 3.14159265358979324f - a : a;
 }
-__device__ __forceinline__ double g_atan2_upper(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ double g_atan2_upper(double y, double x) {
+    const double ax = fabs(x);
+    const double mx = fmax(ax, y), mn = fmin(ax, y);
+    const double z = mn / mx;
+    const double z2 = z * z;
+    double p = kAtan64[15];
+#pragma unroll
+    for (int i = 14; i >= 0; --i) p = fma(p, z2, kAtan64[i]);
+    double a = p * z;
+    a = y > ax ? 1.5707963267948966 - a : a;
+    return x < 0.0 ? 3.141592653589793 - a : a;
+}
 __device__ __forceinline__ float g_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double g_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double g_rsqrt(double x) {
+    // hardware estimate refined by two Newton steps r <- r (3 - x r^2) / 2
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(-0.5 * x, r * r, 1.5);
+    r = r * fma(-0.5 * x, r * r, 1.5);
+    return r;
+}
 
 template <class G> struct GConst;
 template <> struct GConst<float> {
@@ -157,16 +208,33 @@ __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, con
     return c;
 }
 
-// S_lam at a line's sinogram coordinates: sign * (1 + t^2 / f^2) * scale * bilinear(taps).
+// The four taps of a line's bilinear cell (a view holds < 2^31 elements:
+// 32-bit element offset).
 template <class Tap, class G>
-__device__ __forceinline__ float sample_at(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec,
-                                           float inv_f2, float scale) {
-    // a view holds < 2^31 elements: 32-bit element offset
-    const Taps tp = Tap::load(sview + (uint32_t)(c.m * ec.row_elems + c.k + 1));
+__device__ __forceinline__ Taps load_taps(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec) {
+    return Tap::load(sview + (uint32_t)(c.m * ec.row_elems + c.k + 1));
+}
+
+// S_lam from a line's taps: sign * (1 + t^2 / f^2) * scale * bilinear(taps).
+template <class Tap, class G>
+__device__ __forceinline__ float sample_taps(const LineCoord<G> &c, const Taps &tp, float inv_f2, float scale) {
     const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
     const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
     const float B = fmaf(c.fa, r1 - r0, r0);
-    return (c.sgn * scale) * fmaf(c.tf * c.tf, inv_f2, 1.0f) * B;
+    const float sB = Tap::kScaled ? (c.sgn * scale) * B : c.sgn * B;
+    return fmaf(c.tf * c.tf, inv_f2, 1.0f) * sB;
+}
+
+// S_lam at a line's sinogram coordinates.
+template <class Tap, class G>
+__device__ __forceinline__ float sample_at(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec,
+                                           float inv_f2, float scale) {
+    const Taps tp = load_taps<Tap, G>(c, sview, ec);
+    const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
+    const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
+    const float B = fmaf(c.fa, r1 - r0, r0);
+    const float sB = Tap::kScaled ? (c.sgn * scale) * B : c.sgn * B;
+    return fmaf(c.tf * c.tf, inv_f2, 1.0f) * sB;
 }
 
 template <class Tap, class G>

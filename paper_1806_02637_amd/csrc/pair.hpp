@@ -57,13 +57,30 @@ __device__ __forceinline__ void pair_setup(const ViewGeom &A, const ViewGeom &Bv
     pc.inv_f2b = (float)(1.0 / (Bv.f * Bv.f));
 }
 
+// Wave-wide sums with DPP in a fixed order: pairs, quads, half rows and rows
+// of 16 lanes, then row 0 + row 1 into row 1 and rows 0-1 + rows 2-3 into
+// row 3; lane 63 ends with the total, broadcast through a scalar register.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xF, false);
+}
 __device__ __forceinline__ float wave_sum(float x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += __int_as_float(dpp_i<0xB1, 0xF>(__float_as_int(x)));   // quad_perm [1,0,3,2]
+    x += __int_as_float(dpp_i<0x4E, 0xF>(__float_as_int(x)));   // quad_perm [2,3,0,1]
+    x += __int_as_float(dpp_i<0x141, 0xF>(__float_as_int(x)));  // row_half_mirror
+    x += __int_as_float(dpp_i<0x140, 0xF>(__float_as_int(x)));  // row_mirror
+    x += __int_as_float(dpp_i<0x142, 0xA>(__float_as_int(x)));  // row_bcast:15
+    x += __int_as_float(dpp_i<0x143, 0xC>(__float_as_int(x)));  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 __device__ __forceinline__ int wave_sum_i(int x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += dpp_i<0xB1, 0xF>(x);
+    x += dpp_i<0x4E, 0xF>(x);
+    x += dpp_i<0x141, 0xF>(x);
+    x += dpp_i<0x140, 0xF>(x);
+    x += dpp_i<0x142, 0xA>(x);
+    x += dpp_i<0x143, 0xC>(x);
+    return __builtin_amdgcn_readlane(x, 63);
 }
 
 // Pair tiles: the views are cut into blocks of kViewBlock consecutive views and
@@ -102,6 +119,23 @@ __device__ __forceinline__ bool tile_pair(int tile, int q, int n_views, int &a, 
         b = I * kViewBlock + j;
     }
     return a < n_views && b < n_views;
+}
+
+// Stages the constants of every pair of a tile into this wave's LDS slots
+// (lane q loads pair q); empty slots get va = -1.  Wave-scope fences make the
+// slots written by one lane visible to the whole wave.
+template <class G>
+__device__ __forceinline__ void stage_tile(PairConst<G> *slots, const PairConst<G> *tab, int tile, int lane,
+                                           int n_views) {
+    int a, b;
+    if (tile_pair(tile, lane, n_views, a, b)) {
+        slots[lane] = tab[pair_index(a, b, n_views)];
+    } else {
+        slots[lane].va = -1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Logical work item of a block under the XCD-aware numbering.

@@ -1,0 +1,128 @@
+"""Failure handling of the C ABI: every refusal is a status code with a
+message, leaves no partial state, and the context keeps working afterwards.
+(All conditions are forced from the host; no kernel is made to fail.)"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_1806_02637_amd import binding as B
+from paper_1806_02637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def scan_inputs():
+    g = inputs.ScanGeometry(8, 64, 48, 3.0)
+    return g, g.projection_matrices(), g.intrinsics(), inputs.project(g, inputs.random_phantom(3, 4))
+
+
+def _status(fn, *args):
+    try:
+        fn(*args)
+    except B.EccError as e:
+        return e.status, str(e)
+    return B.ECC_OK, ""
+
+
+def test_budget_refusal_leaves_no_state(scan_inputs):
+    import torch  # noqa: F401  (initialises the device)
+
+    _say("case: errors budget")
+    g, P, intr, imgs = scan_inputs
+    ctx = B.ecc_create(0, 1 << 20)  # 1 MiB: the images alone need 98 KiB, sinograms more
+    try:
+        sid = B.ecc_scan_load(ctx, g.n_views, g.W, g.H, P.ctypes.data, intr.ctypes.data, imgs.ctypes.data, 0)
+        before = B.ecc_scan_bytes(ctx, sid)
+        st, msg = _status(B.ecc_scan_build_sinograms, ctx, sid, 720, 513, 0.5, B.ECC_F32, 0)
+        assert st == B.ECC_E_BUDGET and "budget" in msg
+        assert B.ecc_scan_bytes(ctx, sid) == before  # nothing kept from the failed build
+        # a smaller grid fits and works
+        B.ecc_scan_build_sinograms(ctx, sid, 30, 41, 0.5, B.ECC_F32, 0)
+        assert B.ecc_scan_info(ctx, sid)[2:4] == (30, 41)
+        B.ecc_scan_free(ctx, sid)
+    finally:
+        B.ecc_destroy(ctx)
+
+
+def test_argument_and_state_errors(scan_inputs):
+    import torch
+
+    _say("case: errors arguments / state")
+    g, P, intr, imgs = scan_inputs
+    ctx = B.ecc_create(0, 0)
+    try:
+        # mixed detector handedness
+        Pbad = P.copy()
+        Pbad[3, :, 0] *= -1
+        st, _ = _status(B.ecc_scan_load, ctx, g.n_views, g.W, g.H, Pbad.ctypes.data, intr.ctypes.data,
+                        imgs.ctypes.data, 0)
+        assert st == B.ECC_E_ARG
+        Pnan = P.copy()
+        Pnan[1, 2, 3] = np.nan
+        st, _ = _status(B.ecc_scan_load, ctx, g.n_views, g.W, g.H, Pnan.ctypes.data, intr.ctypes.data,
+                        imgs.ctypes.data, 0)
+        assert st == B.ECC_E_ARG
+        sid = B.ecc_scan_load(ctx, g.n_views, g.W, g.H, P.ctypes.data, intr.ctypes.data, imgs.ctypes.data, 0)
+        th = torch.zeros((2, g.n_views, 6), dtype=torch.float64, device="cuda")
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+        prm = B.EvalParams(32, 0, g.default_object_radius(), 0.0)
+        # cost before sinograms exist
+        st, _ = _status(B.ecc_cost, ctx, sid, 2, th.data_ptr(), prm, out.data_ptr(), 0, ws.data_ptr(), ws.numel(), 0)
+        assert st == B.ECC_E_STATE
+        # bad grid / sampling / dtype
+        for args in ((1, 33, 0.5, 0), (40, 2, 0.5, 0), (40, 33, 0.0, 0), (40, 33, 1.5, 0), (40, 33, 0.5, 7)):
+            st, _ = _status(B.ecc_scan_build_sinograms, ctx, sid, *args, 0)
+            assert st == B.ECC_E_ARG, args
+        B.ecc_scan_build_sinograms(ctx, sid, 40, 33, 0.5, B.ECC_F32, 0)
+        st, _ = _status(B.ecc_scan_build_sinograms, ctx, sid, 40, 33, 0.5, B.ECC_F32, 0)
+        assert st == B.ECC_E_STATE  # already built
+        need = B.ecc_workspace_bytes(ctx, sid, 2, 0)
+        for bad in (B.EvalParams(0, 0, 50.0, 0.0), B.EvalParams(5000, 0, 50.0, 0.0), B.EvalParams(32, 0, -1.0, 0.0),
+                    B.EvalParams(32, 3, 50.0, 0.0), B.EvalParams(32, 0, 50.0, math.nan)):
+            st, _ = _status(B.ecc_cost, ctx, sid, 2, th.data_ptr(), bad, out.data_ptr(), 0, ws.data_ptr(), need, 0)
+            assert st == B.ECC_E_ARG
+        st, msg = _status(B.ecc_cost, ctx, sid, 2, th.data_ptr(), prm, out.data_ptr(), 0, ws.data_ptr(), need - 1, 0)
+        assert st == B.ECC_E_ARG and "workspace" in msg
+        st, _ = _status(B.ecc_cost, ctx, sid, 0, th.data_ptr(), prm, out.data_ptr(), 0, ws.data_ptr(), need, 0)
+        assert st == B.ECC_E_ARG
+        st, _ = _status(B.ecc_cost, ctx, 12345, 2, th.data_ptr(), prm, out.data_ptr(), 0, ws.data_ptr(), need, 0)
+        assert st == B.ECC_E_NOSCAN
+        st, _ = _status(B.ecc_scan_read_sinogram, ctx, sid, g.n_views, ctypes.addressof(ctypes.c_float()))
+        assert st == B.ECC_E_ARG
+        # the context still evaluates correctly after all the refusals
+        B.ecc_cost(ctx, sid, 2, th.data_ptr(), prm, out.data_ptr(), 0, ws.data_ptr(), need, 0)
+        torch.cuda.synchronize()
+        assert np.all(np.isfinite(out.cpu().numpy()))
+        B.ecc_scan_free(ctx, sid)
+        st, _ = _status(B.ecc_scan_free, ctx, sid)
+        assert st == B.ECC_E_NOSCAN
+    finally:
+        B.ecc_destroy(ctx)
+
+
+def test_server_argument_errors(scan_inputs):
+    _say("case: errors server")
+    g, P, intr, imgs = scan_inputs
+    ctx = B.ecc_create(0, 0)
+    try:
+        st, _ = _status(B.ecc_server_create, ctx, 0, 1 << 20)
+        assert st == B.ECC_E_ARG
+        st, _ = _status(B.ecc_server_create, ctx, 17, 1 << 20)
+        assert st == B.ECC_E_ARG
+        srv = B.ecc_server_create(ctx, 2, 1 << 24)
+        th = np.zeros((1, g.n_views, 6))
+        st, _ = _status(B.ecc_server_submit, srv, 999, 1, th.ctypes.data, B.EvalParams(32, 0, 50.0, 0.0), 0)
+        assert st == B.ECC_E_NOSCAN
+        st, _ = _status(B.ecc_server_wait, srv, 424242, 0, 0)
+        assert st == B.ECC_E_ARG
+        B.ecc_server_destroy(srv)
+    finally:
+        B.ecc_destroy(ctx)
