@@ -29,6 +29,21 @@ HBM_PEAK_GBS = 8000.0
 TAP_BYTES = {"f32": 4, "bf16": 2, "f16": 2}
 
 
+FWD_SOURCES = ("ecc.hip", "lookup.hpp", "pair.hpp", "projective.hpp", "ecc_internal.hpp", "poly_coeffs.hpp")
+
+
+def fwd_source_hash() -> str:
+    """SHA-256 over the sources the forward kernel is compiled from; HBM counters
+    recorded for another hash describe another kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in FWD_SOURCES:
+        with open(os.path.join(ROOT, "paper_1806_02637_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -185,9 +200,13 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ecc_fwd_full496_traffic.json"))
+    ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (counter calibration) and exit")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(fwd_source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the engine has no multi-GPU path",
               file=sys.stderr)
@@ -254,7 +273,8 @@ def main():
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as fh:
             tj = json.load(fh)
-        if tj.get("workload") == w.name and tj.get("dtype") == args.dtype and tj.get("geom") == args.geom:
+        if (tj.get("workload") == w.name and tj.get("dtype") == args.dtype and tj.get("geom") == args.geom
+                and tj.get("source_sha256") == fwd_source_hash()):
             traffic = tj.get("hbm_bytes_per_launch")
     rec = {
         "metric": METRIC,
