@@ -167,14 +167,20 @@ def measure_serving(eng, n_requests=48, seed=7, load=0.8):
         return [(float(arrivals[i]), scans[kind][j], th, wls[j].K, wls[j].R_mm, g)
                 for i, (j, th, g) in enumerate(reqs)]
 
-    # serial FP32 capacity: back-to-back arrivals on one slot
-    srv = Server(eng, n_slots=1, arena_bytes=4 << 30)
-    _, busy = replay(srv, trace("f32", np.zeros(n_requests)))
-    srv.close()
+    # saturation: every request arrives at once; the serial FP32 makespan
+    # also sets the capacity the Poisson rate is scaled to
+    burst = {}
+    for name, kind, slots in (("serial_f32", "f32", 1), ("served_bf16", "bf16", 4)):
+        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30)
+        _, span = replay(srv, trace(kind, np.zeros(n_requests)))
+        srv.close()
+        burst[name] = {"makespan_s": span, "evals_per_s": evals / span, "slots": slots}
+    busy = burst["serial_f32"]["makespan_s"]
     rate = load * n_requests / busy
     arrivals = poisson_arrivals(rate, n_requests, seed)
     out = {"requests": n_requests, "arrival_rate_per_s": rate, "load_vs_serial_f32_capacity": load,
-           "scans_views": [wl.geom.n_views for wl in wls], "hypotheses_per_request": 64, "grad_fraction": 0.5}
+           "scans_views": [wl.geom.n_views for wl in wls], "hypotheses_per_request": 64, "grad_fraction": 0.5,
+           "burst": burst}
     for name, kind, slots in (("served_bf16", "bf16", 4), ("serial_f32", "f32", 1)):
         srv = Server(eng, n_slots=slots, arena_bytes=8 << 30)
         res, makespan = replay(srv, trace(kind, arrivals))

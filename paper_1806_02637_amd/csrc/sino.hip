@@ -213,14 +213,26 @@ __device__ __forceinline__ double drho_at(const double *G, const float *ext, int
     return sign * (hi - lo) * inv_2dt;
 }
 
+// Largest |value| per view (for the FP16 scale): a workgroup scans 32 rows
+// of one view and issues one atomic max (order-independent, so the result is
+// deterministic).
 __global__ __launch_bounds__(256) void sino_absmax_kernel(const double *G, const float *ext, int n_alpha, int n_t,
                                                           double inv_2dt, uint32_t *absmax) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y, v = blockIdx.z;
+    __shared__ float red[4];
+    const int v = blockIdx.y;
+    const int m0 = blockIdx.x * 32;
+    const int m1 = min(m0 + 32, n_alpha + 1);
     float a = 0.0f;
-    if (k < n_t) a = fabsf((float)drho_at(G, ext, v, m, k, n_alpha, n_t, inv_2dt));
+    for (int m = m0; m < m1; ++m)
+        for (int k = threadIdx.x; k < n_t; k += 256)
+            a = fmaxf(a, fabsf((float)drho_at(G, ext, v, m, k, n_alpha, n_t, inv_2dt)));
     for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off, 64));
-    if ((threadIdx.x & 63) == 0 && a > 0.0f) atomicMax(absmax + v, __float_as_uint(a));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        if (mx > 0.0f) atomicMax(absmax + v, __float_as_uint(mx));
+    }
 }
 
 __device__ __forceinline__ uint16_t to_bf16_rne(float x) {
@@ -282,7 +294,7 @@ hipError_t launch_sino_store(const double *G, const float *ext, int n_views, int
     if (dtype == 2) {
         hipError_t err = hipMemsetAsync(view_absmax, 0, sizeof(uint32_t) * n_views, s);
         if (err != hipSuccess) return err;
-        dim3 g1((n_t + 255) / 256, n_alpha + 1, n_views);
+        dim3 g1((n_alpha + 1 + 31) / 32, n_views);
         hipLaunchKernelGGL(sino_absmax_kernel, g1, dim3(256), 0, s, G, ext, n_alpha, n_t, inv_2dt, view_absmax);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
