@@ -153,9 +153,50 @@ ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double 
                          const ecc_eval_params *params, double *out_cost_dev, float *grad_dev,
                          float *out_pair_grad_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream);
 
+/* The prior route to the same cost, kept for comparison (the method the
+ * paper improves on; Sec. "Introduction" and "Optimized Algorithm"): every
+ * epipolar plane E is mapped to its image line through the pseudo-inverse,
+ * l = P'^{+T} E with P'^{+} = P'^T (P' P'^T)^{-1}, which the caller must
+ * compute for all moved projection matrices P' = P T(theta) before each
+ * evaluation (on the host, as that method does).  The lines equal those of
+ * Eqs. 13-14 up to a positive scale, so the cost equals ecc_cost's to
+ * rounding.  pinv_dev: [B][n_views][4][3] FP64 device, row-major P'^{+} of
+ * hypothesis b, view lam.  Other arguments, the workspace and errors as
+ * ecc_cost (ECC_E_ARG for a NULL pinv_dev). */
+ecc_status ecc_cost_pinv(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev, const double *pinv_dev,
+                         const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
+                         void *workspace_dev, uint64_t workspace_bytes, void *stream);
+
 /* Number of views / pairs and the sinogram grid of a scan (any may be NULL). */
 ecc_status ecc_scan_info(ecc_ctx *ctx, int32_t scan_id, int32_t *n_views, int32_t *n_pairs, int32_t *n_alpha,
                          int32_t *n_t, int32_t *dtype);
+
+/* ---------------------------------------------------------------------------
+ * Motion model of the motion-estimation experiment (Sec. "Optimization"):
+ * each of the 6 rigid parameters of view lam follows an Akima spline
+ * (Akima 1970) through n_nodes nodes placed at view positions node_x, so an
+ * optimiser searches the node values only.  Akima's construction: segment
+ * slopes m_i, two linearly extrapolated slopes beyond each end, node
+ * derivatives (|m_{i+1} - m_i| m_{i-1} + |m_{i-1} - m_{i-2}| m_i) /
+ * (|m_{i+1} - m_i| + |m_{i-1} - m_{i-2}|) (the mean of m_{i-1}, m_i when both
+ * weights vanish), cubic Hermite segments.  FP64.
+ *   node_x: host [n_nodes], strictly ascending, node_x[0] <= 0 and
+ *           node_x[n_nodes - 1] >= n_views - 1; 3 <= n_nodes <= 64.
+ *   nodes_dev: device [B][6][n_nodes] FP64 (parameter order as theta).
+ * Asynchronous on `stream`.  Errors: ECC_E_ARG, ECC_E_HIP.
+ * ------------------------------------------------------------------------- */
+
+/* theta_dev [B][n_views][6] FP64 (device) = the splines at lam = 0 .. n_views - 1. */
+ecc_status ecc_spline_motion(ecc_ctx *ctx, int32_t B, int32_t n_views, int32_t n_nodes, const double *node_x,
+                             const double *nodes_dev, double *theta_dev, void *stream);
+
+/* Chain rule to the nodes: grad_nodes_dev [B][6][n_nodes] FP64 (device,
+ * overwritten) = sum over views of grad_theta_dev [B][n_views][6] FP32 (the
+ * gradient ecc_cost_grad writes) times d theta / d node (exact derivative of
+ * the piecewise-smooth interpolant; summed in view order, deterministic). */
+ecc_status ecc_spline_motion_grad(ecc_ctx *ctx, int32_t B, int32_t n_views, int32_t n_nodes, const double *node_x,
+                                  const double *nodes_dev, const float *grad_theta_dev, double *grad_nodes_dev,
+                                  void *stream);
 
 
 /* ---------------------------------------------------------------------------

@@ -23,8 +23,9 @@ DTYPES = {"f32": ECC_F32, "bf16": ECC_BF16, "f16": ECC_F16}
 SYMBOLS = (
     "ecc_last_error", "ecc_create", "ecc_destroy", "ecc_scan_load", "ecc_scan_build_sinograms",
     "ecc_scan_set_sinograms", "ecc_scan_read_sinogram", "ecc_scan_free", "ecc_scan_bytes", "ecc_workspace_bytes",
-    "ecc_cost", "ecc_cost_grad", "ecc_scan_info", "ecc_server_create", "ecc_server_submit", "ecc_server_poll",
-    "ecc_server_wait", "ecc_server_request_bytes", "ecc_server_destroy",
+    "ecc_cost", "ecc_cost_grad", "ecc_cost_pinv", "ecc_scan_info", "ecc_spline_motion", "ecc_spline_motion_grad",
+    "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_wait", "ecc_server_request_bytes",
+    "ecc_server_destroy",
 )
 
 
@@ -61,7 +62,10 @@ _SIGNATURES = {
     "ecc_workspace_bytes": ([_P, _I32, _I32, _I32, ctypes.POINTER(_U64)], _I32),
     "ecc_cost": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _U64, _P], _I32),
     "ecc_cost_grad": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _P, _U64, _P], _I32),
+    "ecc_cost_pinv": ([_P, _I32, _I32, _P, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _U64, _P], _I32),
     "ecc_scan_info": ([_P, _I32] + [ctypes.POINTER(_I32)] * 5, _I32),
+    "ecc_spline_motion": ([_P, _I32, _I32, _I32, _P, _P, _P, _P], _I32),
+    "ecc_spline_motion_grad": ([_P, _I32, _I32, _I32, _P, _P, _P, _P, _P], _I32),
     "ecc_server_create": ([_P, ctypes.POINTER(_P), _I32, _U64], _I32),
     "ecc_server_submit": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _I32, ctypes.POINTER(ctypes.c_int64)],
                           _I32),
@@ -159,10 +163,28 @@ def ecc_cost_grad(ctx: int, scan_id: int, B: int, theta_ptr: int, params: EvalPa
                                         out_pair_grad_ptr, workspace_ptr, workspace_bytes, stream), "ecc_cost_grad")
 
 
+def ecc_cost_pinv(ctx: int, scan_id: int, B: int, theta_ptr: int, pinv_ptr: int, params: EvalParams,
+                  out_cost_ptr: int, out_pair_ptr: int, workspace_ptr: int, workspace_bytes: int, stream: int = 0):
+    _check(load_library().ecc_cost_pinv(ctx, scan_id, B, theta_ptr, pinv_ptr, ctypes.byref(params), out_cost_ptr,
+                                        out_pair_ptr, workspace_ptr, workspace_bytes, stream), "ecc_cost_pinv")
+
+
 def ecc_scan_info(ctx: int, scan_id: int):
     vals = [_I32() for _ in range(5)]
     _check(load_library().ecc_scan_info(ctx, scan_id, *[ctypes.byref(v) for v in vals]), "ecc_scan_info")
     return tuple(v.value for v in vals)
+
+
+def ecc_spline_motion(ctx: int, B: int, n_views: int, n_nodes: int, node_x_ptr: int, nodes_ptr: int,
+                      theta_ptr: int, stream: int = 0):
+    _check(load_library().ecc_spline_motion(ctx, B, n_views, n_nodes, node_x_ptr, nodes_ptr, theta_ptr, stream),
+           "ecc_spline_motion")
+
+
+def ecc_spline_motion_grad(ctx: int, B: int, n_views: int, n_nodes: int, node_x_ptr: int, nodes_ptr: int,
+                           grad_theta_ptr: int, grad_nodes_ptr: int, stream: int = 0):
+    _check(load_library().ecc_spline_motion_grad(ctx, B, n_views, n_nodes, node_x_ptr, nodes_ptr, grad_theta_ptr,
+                                                 grad_nodes_ptr, stream), "ecc_spline_motion_grad")
 
 
 def ecc_server_create(ctx: int, n_slots: int, arena_bytes: int) -> int:

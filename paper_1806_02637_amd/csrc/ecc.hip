@@ -106,7 +106,8 @@ size_t pair_const_bytes(bool geom64) { return geom64 ? sizeof(PairConst<double>)
 // wave-uniform (scalar) loads.
 template <class G>
 __global__ __launch_bounds__(256) void pair_setup_kernel(const float *__restrict__ vscale,
-                                                         const ViewGeom *__restrict__ vt, EvalConsts ec,
+                                                         const ViewGeom *__restrict__ vt,
+                                                         const double *__restrict__ pinv, EvalConsts ec,
                                                          PairConst<G> *__restrict__ table) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)ec.B * ec.n_pairs) return;
@@ -115,7 +116,9 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(const float *__restrict
     int a, b;
     pair_from_index(p, ec.n_views, a, b);
     PairConst<G> pc;
-    pair_setup<G>(vt[(int64_t)hyp * ec.n_views + a], vt[(int64_t)hyp * ec.n_views + b], ec.R_mm, ec.K, pc);
+    const int64_t ga = (int64_t)hyp * ec.n_views + a, gb = (int64_t)hyp * ec.n_views + b;
+    pair_setup<G>(vt[ga], vt[gb], ec.R_mm, ec.K, pc, pinv ? pinv + 12 * ga : nullptr,
+                  pinv ? pinv + 12 * gb : nullptr);
     pc.va = a;
     pc.vb = b;
     pc.sa = vscale[a];
@@ -124,24 +127,69 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(const float *__restrict
 }
 
 template <class G>
-static hipError_t launch_pair_setup_t(const float *vscale, const ViewGeom *vt, EvalConsts ec, void *table,
-                                      hipStream_t s) {
+static hipError_t launch_pair_setup_t(const float *vscale, const ViewGeom *vt, const double *pinv, EvalConsts ec,
+                                      void *table, hipStream_t s) {
     const int64_t n = (int64_t)ec.B * ec.n_pairs;
-    hipLaunchKernelGGL(pair_setup_kernel<G>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vscale, vt, ec,
-                       (PairConst<G> *)table);
+    hipLaunchKernelGGL(pair_setup_kernel<G>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vscale, vt, pinv,
+                       ec, (PairConst<G> *)table);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s) {
-    return ec.geom64 ? launch_pair_setup_t<double>(view_scale, vt, ec, table, s)
-                     : launch_pair_setup_t<float>(view_scale, vt, ec, table, s);
+hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s,
+                             const double *pinv) {
+    return ec.geom64 ? launch_pair_setup_t<double>(view_scale, vt, pinv, ec, table, s)
+                     : launch_pair_setup_t<float>(view_scale, vt, pinv, ec, table, s);
+}
+
+// One plane of one pair between issuing its gathers and combining them: the
+// taps in flight plus everything the combine needs (bilinear fractions,
+// Grangeat weights with the storage scale, hit test, relative fold sign).
+struct PlaneInFlight {
+    Taps ta, tb;
+    float fa_a, ft_a, w_a, fa_b, ft_b, w_b;
+    bool hit, flip;
+    uint64_t mask;  // wave mask of `hit`
+};
+
+template <class Tap, class G>
+__device__ __forceinline__ void issue_plane(PlaneInFlight &P, const PairConst<G> &pc, G cs, G sn, const Tap *sa,
+                                            const Tap *sb, const EvalConsts &ec) {
+    const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
+    const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
+    P.ta = load_taps<Tap, G>(ca, sa, ec);
+    P.tb = load_taps<Tap, G>(cb, sb, ec);
+    P.fa_a = ca.fa;
+    P.ft_a = ca.ft;
+    P.fa_b = cb.fa;
+    P.ft_b = cb.ft;
+    P.w_a = grangeat_weight<Tap>(ca.tf, pc.inv_f2a, pc.sa);
+    P.w_b = grangeat_weight<Tap>(cb.tf, pc.inv_f2b, pc.sb);
+    P.hit = ca.hit & cb.hit;
+    P.flip = ca.fold != cb.fold;
+    P.mask = hit_mask(ca) & hit_mask(cb);
+}
+
+// Adds (S_a - S_b)^2 of a plane whose taps have arrived.  (S_a - S_b)^2 =
+// (U_a -+ U_b)^2 with U the unsigned samples: only the relative fold sign
+// matters.  `valid` masks the lanes past K in the last sweep, `count_mask`
+// the same lanes in the hit count.
+__device__ __forceinline__ void combine_plane(const PlaneInFlight &P, bool valid, uint64_t count_mask, float &acc,
+                                              int &cnt) {
+    const float Ua = P.w_a * bilerp(P.ta, P.fa_a, P.ft_a);
+    const float Ub = P.w_b * bilerp(P.tb, P.fa_b, P.ft_b);
+    const float d = (P.hit & valid) ? Ua - (P.flip ? -Ub : Ub) : 0.0f;
+    acc = fmaf(d, d, acc);
+    cnt += __popcll(P.mask & count_mask);
 }
 
 // A wave = one hypothesis x one pair tile; a workgroup = 4 hypotheses of the
-// same tile (they read nearly the same sinogram cells).  UNROLL2 walks two
-// planes per iteration (two independent gather chains); UNIFORM moves the
-// pair constants from LDS into scalar registers.
-template <class Tap, class G, bool UNROLL2, bool UNIFORM>
+// same tile (they read nearly the same sinogram cells).  UNIFORM moves the
+// pair constants from LDS into scalar registers.  Lanes walk the planes
+// k = lane + 64 i; the trip count is wave-uniform (K / 64 full sweeps plus a
+// masked tail) and the hit count is a population count of the hit mask.
+// PIPE issues the gathers of sweep i + 1 before combining sweep i, so each
+// wave keeps two planes' gathers in flight.
+template <class Tap, class G, bool UNIFORM, bool PIPE>
 __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ sino,
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
                                                       float *__restrict__ out_pair, double *__restrict__ partials,
@@ -159,6 +207,10 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     stage_tile(slots[wave], table + (int64_t)hyp * ec.n_pairs, tile, lane, ec.n_views);
 
     const Tap *base = (const Tap *)sino;
+    const bool has_tail = (ec.K & 63) != 0;
+    const int n_sweeps = (ec.K >> 6) + (has_tail ? 1 : 0);
+    const bool in_tail = lane < (ec.K & 63);
+    const uint64_t tail_mask = (1ull << (ec.K & 63)) - 1;
     double wave_acc = 0.0;
     for (int q = 0; q < kPairsPerWave; ++q) {
         const PairConst<G> pc = UNIFORM ? uniform(slots[wave][q]) : slots[wave][q];
@@ -170,47 +222,57 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
         float acc = 0.0f;
         int cnt = 0;
         // plane angle of this lane, advanced by one wave step (64 dk) per
-        // plane through the rotation (rc, rs)
+        // sweep through the rotation (rc, rs)
         G sn, cs;
         g_sincos(pc.k0 + (G)lane * pc.dk, &sn, &cs);
-        int k = lane;
-        if (UNROLL2) {
-            for (; k + 64 < ec.K; k += 128) {
-                const G cs2 = cs * pc.rc - sn * pc.rs;
-                const G sn2 = sn * pc.rc + cs * pc.rs;
-                bool ha0, hb0, ha1, hb1;
-                const float Sa0 = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, ha0);
-                const float Sb0 = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hb0);
-                const float Sa1 = lookup<Tap, G>(pc.ha, cs2, sn2, sa, ec, pc.inv_f2a, pc.sa, ha1);
-                const float Sb1 = lookup<Tap, G>(pc.hb, cs2, sn2, sb, ec, pc.inv_f2b, pc.sb, hb1);
-                const float d0 = Sa0 - Sb0, d1 = Sa1 - Sb1;
-                if (ha0 && hb0) {
-                    acc = fmaf(d0, d0, acc);
-                    ++cnt;
-                }
-                if (ha1 && hb1) {
-                    acc = fmaf(d1, d1, acc);
-                    ++cnt;
-                }
-                cs = cs2 * pc.rc - sn2 * pc.rs;
-                sn = sn2 * pc.rc + cs2 * pc.rs;
-            }
-        }
-        for (; k < ec.K; k += 64) {
-            bool ha0, hb0;
-            const float Sa0 = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, ha0);
-            const float Sb0 = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hb0);
-            if (ha0 && hb0) {
-                const float d0 = Sa0 - Sb0;
-                acc = fmaf(d0, d0, acc);
-                ++cnt;
-            }
+        auto rotate = [&]() {
             const G c2 = cs * pc.rc - sn * pc.rs;
             sn = sn * pc.rc + cs * pc.rs;
             cs = c2;
+        };
+        // sweep i is the partial last one when has_tail and i = n_sweeps - 1
+        auto combine = [&](const PlaneInFlight &P, int i) {
+            const bool last = has_tail & (i == n_sweeps - 1);
+            combine_plane(P, !last | in_tail, last ? tail_mask : ~0ull, acc, cnt);
+        };
+        if (PIPE) {
+            // two buffers, swapped by unrolling (no register copies); the
+            // steady state issues unconditionally so that each combine waits
+            // only for its own gathers
+            PlaneInFlight P0, P1;
+            issue_plane<Tap, G>(P0, pc, cs, sn, sa, sb, ec);
+            rotate();
+            int i = 0;
+            // (the scheduling barriers keep the compiler from hoisting a
+            // combine above the issue that is meant to cover its latency)
+            for (; i + 2 < n_sweeps; i += 2) {
+                issue_plane<Tap, G>(P1, pc, cs, sn, sa, sb, ec);
+                rotate();
+                __builtin_amdgcn_sched_barrier(0);
+                combine(P0, i);
+                issue_plane<Tap, G>(P0, pc, cs, sn, sa, sb, ec);
+                rotate();
+                __builtin_amdgcn_sched_barrier(0);
+                combine(P1, i + 1);
+            }
+            if (i + 1 < n_sweeps) {
+                issue_plane<Tap, G>(P1, pc, cs, sn, sa, sb, ec);
+                __builtin_amdgcn_sched_barrier(0);
+                combine(P0, i);
+                combine(P1, i + 1);
+            } else {
+                combine(P0, i);
+            }
+        } else {
+#pragma unroll 1
+            for (int i = 0; i < n_sweeps; ++i) {
+                PlaneInFlight P;
+                issue_plane<Tap, G>(P, pc, cs, sn, sa, sb, ec);
+                rotate();
+                combine(P, i);
+            }
         }
         acc = wave_sum(acc);
-        cnt = wave_sum_i(cnt);
         const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
         const float e = ec.inv_c > 0.0f ? d / (1.0f + d * ec.inv_c) : d;
         if (out_pair && lane == 0) out_pair[(int64_t)hyp * ec.n_pairs + p] = e;
@@ -241,23 +303,23 @@ size_t occupancy_lds_bytes(size_t static_bytes) {
     return b > static_bytes ? b - static_bytes : 0;
 }
 
-template <class Tap, class G, bool UNROLL2, bool UNIFORM>
+template <class Tap, class G, bool UNIFORM, bool PIPE>
 static hipError_t launch_fwd_v(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
                                int n_tiles, hipStream_t s) {
     const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
     const int64_t blocks = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G, UNROLL2, UNIFORM>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
+    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G, UNIFORM, PIPE>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
                        occupancy_lds_bytes(sizeof(PairConst<G>) * kPairsPerWave * kWavesPerBlock), s, sino,
                        (const PairConst<G> *)table, ec, out_pair, partials, n_tiles);
     return hipGetLastError();
 }
 
-// Plane-loop variant of the FP32 path (bit 0: two planes per iteration,
-// bit 1: pair constants in scalar registers); ECC_FWD_VARIANT overrides.
+// Plane-loop variant: bit 1 (2) pair constants in scalar registers (else
+// LDS), bit 2 (4) two planes' gathers in flight; ECC_FWD_VARIANT overrides.
 static int fwd_variant() {
     static int v = [] {
         const char *e = getenv("ECC_FWD_VARIANT");
-        return e ? atoi(e) & 3 : kDefaultFwdVariant;
+        return e ? atoi(e) & 6 : kDefaultFwdVariant;
     }();
     return v;
 }
@@ -266,9 +328,9 @@ template <class Tap, class G>
 static hipError_t launch_fwd_t(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
                                int n_tiles, hipStream_t s) {
     switch (fwd_variant()) {
-        case 1: return launch_fwd_v<Tap, G, true, false>(sino, table, ec, out_pair, partials, n_tiles, s);
-        case 2: return launch_fwd_v<Tap, G, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
-        case 3: return launch_fwd_v<Tap, G, true, true>(sino, table, ec, out_pair, partials, n_tiles, s);
+        case 2: return launch_fwd_v<Tap, G, true, false>(sino, table, ec, out_pair, partials, n_tiles, s);
+        case 4: return launch_fwd_v<Tap, G, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
+        case 6: return launch_fwd_v<Tap, G, true, true>(sino, table, ec, out_pair, partials, n_tiles, s);
         default: return launch_fwd_v<Tap, G, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
     }
 }

@@ -63,8 +63,9 @@ struct EvalConsts {
     double R_mm;
     float inv_c;       // 1/c, 0 for c = inf
     float half_w, half_h;
-    float t_max, inv_dt, inv_dalpha;
-    double t_max_d, inv_dt_d, inv_dalpha_d;
+    // t0 = t_max + dt: (t + t0) / dt is the stored column coordinate of t
+    float t0, inv_dt, inv_dalpha;
+    double t0_d, inv_dt_d, inv_dalpha_d;
 };
 
 // Pair index <-> (a, b), a < b, row-major triangle.
@@ -86,7 +87,10 @@ hipError_t launch_view_setup(const double *P, const double *intr, const double *
                              ViewGeom *vt, ViewGeomGrad *vg, hipStream_t s);
 // per-pair constant table: [B][n_pairs] PairConst<float> or PairConst<double>
 size_t pair_const_bytes(bool geom64);
-hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s);
+// pinv (optional): [B][n_views][4][3] pseudo-inverses of the moved P' (the
+// line route the method replaces)
+hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s,
+                             const double *pinv = nullptr);
 hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
                           double *partials, int n_tiles, hipStream_t s);
 // adjoint: plane kernel -> per-pair sensitivities sens [B][n_pairs][13], then
@@ -96,6 +100,20 @@ hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *v
                           hipStream_t s);
 hipError_t launch_reduce_cost(const double *partials, int n_tiles, int B, double *out_cost, hipStream_t s);
 hipError_t launch_reduce_grad(const float *pair_grad, int B, int n_views, float *grad, hipStream_t s);
+
+// Akima spline motion model (spline.hip): node positions along the view
+// index, strictly ascending, covering [0, n_views - 1].
+constexpr int kMaxSplineNodes = 64;
+struct SplineKnots {
+    int32_t n;
+    double x[kMaxSplineNodes];
+};
+// nodes [B][6][n] -> theta [B][n_views][6]
+hipError_t launch_spline_motion(const SplineKnots &kn, int B, int n_views, const double *nodes, double *theta,
+                                hipStream_t s);
+// grad_theta [B][n_views][6] -> grad_nodes [B][6][n]
+hipError_t launch_spline_grad(const SplineKnots &kn, int B, int n_views, const double *nodes,
+                              const float *grad_theta, double *grad_nodes, hipStream_t s);
 
 // Engine services shared with the server (engine.hip).
 int ctx_device(struct ::ecc_ctx *ctx);
@@ -108,7 +126,7 @@ constexpr int kWavesPerBlock = 4;
 // default cap on resident plane-kernel workgroups per CU (0 = no cap)
 constexpr int kDefaultBlocksPerCU = 4;
 // default plane-loop variant of the FP32 forward kernel (see ecc.hip)
-constexpr int kDefaultFwdVariant = 2;
+constexpr int kDefaultFwdVariant = 4;
 // dynamic LDS that, added to a kernel's static LDS, enforces the cap
 size_t occupancy_lds_bytes(size_t static_bytes);
 

@@ -184,10 +184,10 @@ EvalConsts make_consts(const Scan *s, int B, const ecc_eval_params *prm) {
     const double t_max = 0.5 * sqrt((double)s->W * s->W + (double)s->H * s->H);
     const double dt = 2.0 * t_max / (s->layout.n_t - 1);
     const double dalpha = M_PI / s->layout.n_alpha;
-    ec.t_max_d = t_max;
+    ec.t0_d = t_max + dt;
     ec.inv_dt_d = 1.0 / dt;
     ec.inv_dalpha_d = 1.0 / dalpha;
-    ec.t_max = (float)t_max;
+    ec.t0 = (float)(t_max + dt);
     ec.inv_dt = (float)(1.0 / dt);
     ec.inv_dalpha = (float)(1.0 / dalpha);
     return ec;
@@ -362,7 +362,7 @@ static ecc_status install_sinograms(ecc_ctx *ctx, Scan *s, int32_t n_alpha, int3
 ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, double ds_px,
                                     int32_t dtype, void *stream) {
     if (!ctx) return fail(ECC_E_ARG, "null context");
-    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 31))
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 28))
         return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
     if (!(ds_px > 0.0) || ds_px > 1.0) return fail(ECC_E_ARG, "ds_px must be in (0, 1]");
     if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
@@ -377,7 +377,7 @@ ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alp
 ecc_status ecc_scan_set_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, const float *sino,
                                   int32_t sino_on_device, int32_t dtype) {
     if (!ctx || !sino) return fail(ECC_E_ARG, "null argument");
-    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 31))
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 28))
         return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
     if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
     DeviceGuard g(ctx->device);
@@ -442,6 +442,47 @@ ecc_status ecc_scan_info(ecc_ctx *ctx, int32_t scan_id, int32_t *n_views, int32_
     return ok();
 }
 
+static ecc_status check_spline(ecc_ctx *ctx, int32_t B, int32_t n_views, int32_t n_nodes, const double *node_x,
+                               SplineKnots *kn) {
+    if (!ctx || !node_x) return fail(ECC_E_ARG, "null argument");
+    if (B < 1 || B > 65536) return fail(ECC_E_ARG, "B = %d out of range [1, 65536]", B);
+    if (n_views < 2 || n_views > 65536) return fail(ECC_E_ARG, "n_views = %d out of range [2, 65536]", n_views);
+    if (n_nodes < 3 || n_nodes > kMaxSplineNodes)
+        return fail(ECC_E_ARG, "n_nodes = %d out of range [3, %d]", n_nodes, kMaxSplineNodes);
+    kn->n = n_nodes;
+    for (int j = 0; j < n_nodes; ++j) {
+        if (!isfinite(node_x[j])) return fail(ECC_E_ARG, "non-finite node position %d", j);
+        if (j > 0 && !(node_x[j] > node_x[j - 1])) return fail(ECC_E_ARG, "node positions must ascend strictly");
+        kn->x[j] = node_x[j];
+    }
+    if (node_x[0] > 0.0 || node_x[n_nodes - 1] < (double)(n_views - 1))
+        return fail(ECC_E_ARG, "nodes must cover the views [0, %d]", n_views - 1);
+    return ECC_OK;
+}
+
+ecc_status ecc_spline_motion(ecc_ctx *ctx, int32_t B, int32_t n_views, int32_t n_nodes, const double *node_x,
+                             const double *nodes_dev, double *theta_dev, void *stream) {
+    SplineKnots kn;
+    ecc_status st = check_spline(ctx, B, n_views, n_nodes, node_x, &kn);
+    if (st != ECC_OK) return st;
+    if (!nodes_dev || !theta_dev) return fail(ECC_E_ARG, "null argument");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(launch_spline_motion(kn, B, n_views, nodes_dev, theta_dev, (hipStream_t)stream));
+    return ok();
+}
+
+ecc_status ecc_spline_motion_grad(ecc_ctx *ctx, int32_t B, int32_t n_views, int32_t n_nodes, const double *node_x,
+                                  const double *nodes_dev, const float *grad_theta_dev, double *grad_nodes_dev,
+                                  void *stream) {
+    SplineKnots kn;
+    ecc_status st = check_spline(ctx, B, n_views, n_nodes, node_x, &kn);
+    if (st != ECC_OK) return st;
+    if (!nodes_dev || !grad_theta_dev || !grad_nodes_dev) return fail(ECC_E_ARG, "null argument");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(launch_spline_grad(kn, B, n_views, nodes_dev, grad_theta_dev, grad_nodes_dev, (hipStream_t)stream));
+    return ok();
+}
+
 ecc_status ecc_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, int32_t B, int32_t with_grad, uint64_t *bytes) {
     if (!ctx || !bytes) return fail(ECC_E_ARG, "null argument");
     if (B < 1 || B > 65536) return fail(ECC_E_ARG, "B = %d out of range [1, 65536]", B);
@@ -452,9 +493,28 @@ ecc_status ecc_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, int32_t B, int32_t
     return ok();
 }
 
+static ecc_status cost_impl(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                            const double *pinv_dev, const ecc_eval_params *params, double *out_cost_dev,
+                            float *out_pair_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream);
+
 ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev, const ecc_eval_params *params,
                     double *out_cost_dev, float *out_pair_dev, void *workspace_dev, uint64_t workspace_bytes,
                     void *stream) {
+    return cost_impl(ctx, scan_id, B, theta_dev, nullptr, params, out_cost_dev, out_pair_dev, workspace_dev,
+                     workspace_bytes, stream);
+}
+
+ecc_status ecc_cost_pinv(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev, const double *pinv_dev,
+                         const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
+                         void *workspace_dev, uint64_t workspace_bytes, void *stream) {
+    if (!pinv_dev) return fail(ECC_E_ARG, "null pseudo-inverse pointer");
+    return cost_impl(ctx, scan_id, B, theta_dev, pinv_dev, params, out_cost_dev, out_pair_dev, workspace_dev,
+                     workspace_bytes, stream);
+}
+
+static ecc_status cost_impl(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                            const double *pinv_dev, const ecc_eval_params *params, double *out_cost_dev,
+                            float *out_pair_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream) {
     if (!ctx) return fail(ECC_E_ARG, "null context");
     // the lock spans the (asynchronous) launches so that a concurrent
     // ecc_scan_free cannot release the scan between check and launch
@@ -476,7 +536,7 @@ ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *thet
     const int n_tiles = n_tiles_for(ec.n_views);
     void *table = ws + w.table_off;
     HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, nullptr, hs));
-    HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs));
+    HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs, pinv_dev));
     HIP_TRY(launch_ecc_fwd(s->sino_dev, table, ec, s->layout.dtype, out_pair_dev, partials, n_tiles, hs));
     HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
     return ok();

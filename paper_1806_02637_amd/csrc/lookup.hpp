@@ -115,30 +115,33 @@ __device__ __forceinline__ void g_sincos(float x, float *s, float *c) {
 }
 __device__ __forceinline__ void g_sincos(double x, double *s, double *c) { sincos(x, s, c); }
 
-// Angle of (x, y) for y >= 0, in [0, pi].
-__device__ __forceinline__ float g_atan2_upper(float y, float x) {
-    const float ax = fabsf(x);
-    const float mx = fmaxf(ax, y), mn = fminf(ax, y);
-    const float z = mn * __builtin_amdgcn_rcpf(mx);
-    const float z2 = z * z;
-    float p = kAtan[7];
+// Angle in [0, pi] of a line's normal (x, y), y >= 0, given |x|, |y|,
+// 1 / |(x, y)| and whether x < 0.  The base angle is the one of the smaller
+// component, theta = atan(min / max) in [0, pi/4]; then
+//   swap (|y| > |x|): pi/2 - theta;  xneg: pi - (...)
+// combined as off + sgn theta with off in {0, pi/2, pi} and sgn = +-1.
+// FP32 takes theta = asin(min / |(x, y)|) by the fitted polynomial (no
+// reciprocal: the inverse norm is shared with t); FP64 takes atan(min / max).
+__device__ __forceinline__ float g_angle(float ax, float ay, float rinv, bool xneg) {
+    const bool swap = ay > ax;
+    const float s = (swap ? ax : ay) * rinv;
+    const float s2 = s * s;
+    float p = kAsin[7];
 #pragma unroll
-    for (int i = 6; i >= 0; --i) p = fmaf(p, z2, kAtan[i]);
-    float a = p * z;
-    a = y > ax ? 1.57079632679489662f - a : a;
-    return x < 0.0f ? 3.14159265358979324f - a : a;
+    for (int i = 6; i >= 0; --i) p = fmaf(p, s2, kAsin[i]);
+    const float off = swap ? 1.57079632679489662f : (xneg ? 3.14159265358979324f : 0.0f);
+    return fmaf(swap != xneg ? -s : s, p, off);
 }
-__device__ __forceinline__ double g_atan2_upper(double y, double x) {
-    const double ax = fabs(x);
-    const double mx = fmax(ax, y), mn = fmin(ax, y);
+__device__ __forceinline__ double g_angle(double ax, double ay, double, bool xneg) {
+    const double mx = fmax(ax, ay), mn = fmin(ax, ay);
+    const bool swap = ay > ax;
     const double z = mn / mx;
     const double z2 = z * z;
     double p = kAtan64[15];
 #pragma unroll
     for (int i = 14; i >= 0; --i) p = fma(p, z2, kAtan64[i]);
-    double a = p * z;
-    a = y > ax ? 1.5707963267948966 - a : a;
-    return x < 0.0 ? 3.141592653589793 - a : a;
+    const double off = swap ? 1.5707963267948966 : (xneg ? 3.141592653589793 : 0.0);
+    return fma(swap != xneg ? -z : z, p, off);
 }
 __device__ __forceinline__ float g_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double g_rsqrt(double x) {
@@ -149,14 +152,19 @@ __device__ __forceinline__ double g_rsqrt(double x) {
     return r;
 }
 
+// Clamp to [lo, hi]; the FP32 form is one median-of-three (a NaN input
+// yields lo or NaN, and NaN converts to index 0: addresses stay in range).
+__device__ __forceinline__ float g_clamp(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double g_clamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
+
 template <class G> struct GConst;
 template <> struct GConst<float> {
-    static __device__ __forceinline__ float t_max(const EvalConsts &e) { return e.t_max; }
+    static __device__ __forceinline__ float t0(const EvalConsts &e) { return e.t0; }
     static __device__ __forceinline__ float inv_dt(const EvalConsts &e) { return e.inv_dt; }
     static __device__ __forceinline__ float inv_dalpha(const EvalConsts &e) { return e.inv_dalpha; }
 };
 template <> struct GConst<double> {
-    static __device__ __forceinline__ double t_max(const EvalConsts &e) { return e.t_max_d; }
+    static __device__ __forceinline__ double t0(const EvalConsts &e) { return e.t0_d; }
     static __device__ __forceinline__ double inv_dt(const EvalConsts &e) { return e.inv_dt_d; }
     static __device__ __forceinline__ double inv_dalpha(const EvalConsts &e) { return e.inv_dalpha_d; }
 };
@@ -172,69 +180,103 @@ __device__ __forceinline__ double g_flip(double x, bool f) { return f ? -x : x; 
 template <class G>
 struct LineCoord {
     G l1, l2, l3, rinv;  // folded line, 1/|(l1, l2)|
-    float sgn;           // -1 when the line was folded
+    G r2, edge;          // |(l1, l2)|^2, (W/2)|l1| + (H/2)|l2|
     float fa, ft, tf;    // bilinear fractions, folded t (FP32)
-    int m, k;            // floor cell (clamped for memory safety)
-    bool hit;
+    int m, j;            // cell: row m, stored column j = k + 1 (clamped for memory safety)
+    bool hit, fold;      // fold: the line was negated (sign -1 on S)
 };
 
 template <class G>
 __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, const EvalConsts &ec) {
     LineCoord<G> c;
-    G l1 = h[0] * cs + h[3] * sn;
-    G l2 = h[1] * cs + h[4] * sn;
-    G l3 = h[2] * cs + h[5] * sn;
-    const bool fold = (l2 < (G)0) | ((l2 == (G)0) & (l1 < (G)0));  // no short-circuit: stays branch-free
+    const G l1 = h[0] * cs + h[3] * sn;
+    const G l2 = h[1] * cs + h[4] * sn;
+    const G l3 = h[2] * cs + h[5] * sn;
+    // fold when l2 < 0; a line with l2 = 0 keeps alpha in {0, pi}, and
+    // alpha = pi reads the pad row, which holds the folded values
+    const bool fold = l2 < (G)0;
+    c.fold = fold;
     c.l1 = g_flip(l1, fold);
     c.l2 = g_flip(l2, fold);
     c.l3 = g_flip(l3, fold);
-    c.sgn = fold ? -1.0f : 1.0f;
-    const G r2 = c.l1 * c.l1 + c.l2 * c.l2;
+    const G r2 = l1 * l1 + l2 * l2;
+    c.r2 = r2;
     c.rinv = g_rsqrt(r2);
-    const G alpha = g_atan2_upper(fabs(c.l2), c.l1);
+    // the folded l1 is negative iff exactly one of (l1 < 0, fold) holds; at
+    // l1 = 0 both quadrant choices give pi/2
+    const G alpha = g_angle(fabs(l1), fabs(l2), c.rinv, (l1 < (G)0) != fold);
     const G t = -c.l3 * c.rinv;
     // closed detector rectangle of pixel edges:
     // |t| <= (W/2)|cos a| + (H/2)|sin a|  <=>  |l3| <= (W/2)|l1| + (H/2)|l2|
-    c.hit = (r2 > (G)0) && (fabs(c.l3) <= (G)ec.half_w * fabs(c.l1) + (G)ec.half_h * fabs(c.l2));
+    c.edge = (G)ec.half_w * fabs(l1) + (G)ec.half_h * fabs(l2);
+    c.hit = (r2 > (G)0) & (fabs(l3) <= c.edge);
     const G aa = alpha * GConst<G>::inv_dalpha(ec);
-    const G mf = fmin(fmax(floor(aa), (G)0), (G)(ec.n_alpha - 1));
-    const G tau = (t + GConst<G>::t_max(ec)) * GConst<G>::inv_dt(ec);
-    const G kf = fmin(fmax(floor(tau), (G)-1), (G)(ec.n_t - 1));
+    const G mf = g_clamp(floor(aa), (G)0, (G)(ec.n_alpha - 1));
+    // stored column coordinate: column j holds t_{j-1}, so j = tau + 1 with
+    // tau = (t + t_max) / dt; t0 = t_max + dt
+    const G tau = (t + GConst<G>::t0(ec)) * GConst<G>::inv_dt(ec);
+    const G jf = g_clamp(floor(tau), (G)0, (G)ec.n_t);
     c.fa = (float)(aa - mf);
-    c.ft = (float)(tau - kf);
+    c.ft = (float)(tau - jf);
     c.m = (int)mf;
-    c.k = (int)kf;
+    c.j = (int)jf;
     c.tf = (float)t;
     return c;
 }
 
-// The four taps of a line's bilinear cell (a view holds < 2^31 elements:
-// 32-bit element offset).
+// The same hit test as a wave mask (the comparisons are shared with
+// LineCoord::hit; inactive lanes read 0).
+__device__ __forceinline__ uint64_t g_cmp_gt(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 2); }
+__device__ __forceinline__ uint64_t g_cmp_le(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 5); }
+__device__ __forceinline__ uint64_t g_cmp_gt(double a, double b) { return __builtin_amdgcn_fcmp(a, b, 2); }
+__device__ __forceinline__ uint64_t g_cmp_le(double a, double b) { return __builtin_amdgcn_fcmp(a, b, 5); }
+template <class G>
+__device__ __forceinline__ uint64_t hit_mask(const LineCoord<G> &c) {
+    return g_cmp_gt(c.r2, (G)0) & g_cmp_le(fabs(c.l3), c.edge);
+}
+
+// The four taps of a line's bilinear cell.  A view holds < 2^28 elements, so
+// the byte offset is a 32-bit value added to the view's base address, and
+// m, j < 2^24 allow the 24-bit multiply-add.
 template <class Tap, class G>
 __device__ __forceinline__ Taps load_taps(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec) {
-    return Tap::load(sview + (uint32_t)(c.m * ec.row_elems + c.k + 1));
+    const uint32_t e = __umul24((uint32_t)c.m, (uint32_t)ec.row_elems) + (uint32_t)c.j;
+    return Tap::load((const Tap *)((const char *)sview + e * (uint32_t)sizeof(Tap)));
+}
+
+// Bilinear interpolation of a cell's taps at fractions (fa along alpha, ft
+// along t).
+__device__ __forceinline__ float bilerp(const Taps &tp, float fa, float ft) {
+    const float r0 = fmaf(ft, tp.s01 - tp.s00, tp.s00);
+    const float r1 = fmaf(ft, tp.s11 - tp.s10, tp.s10);
+    return fmaf(fa, r1 - r0, r0);
+}
+
+// Grangeat weight 1 + t^2 / f^2, times the storage scale of scaled types.
+template <class Tap>
+__device__ __forceinline__ float grangeat_weight(float t, float inv_f2, float scale) {
+    const float w = fmaf(t * t, inv_f2, 1.0f);
+    return Tap::kScaled ? w * scale : w;
+}
+
+// |S_lam| up to the fold sign: (1 + t^2 / f^2) * scale * bilinear(taps).
+template <class Tap, class G>
+__device__ __forceinline__ float sample_unsigned(const LineCoord<G> &c, const Taps &tp, float inv_f2, float scale) {
+    return grangeat_weight<Tap>(c.tf, inv_f2, scale) * bilerp(tp, c.fa, c.ft);
 }
 
 // S_lam from a line's taps: sign * (1 + t^2 / f^2) * scale * bilinear(taps).
 template <class Tap, class G>
 __device__ __forceinline__ float sample_taps(const LineCoord<G> &c, const Taps &tp, float inv_f2, float scale) {
-    const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
-    const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
-    const float B = fmaf(c.fa, r1 - r0, r0);
-    const float sB = Tap::kScaled ? (c.sgn * scale) * B : c.sgn * B;
-    return fmaf(c.tf * c.tf, inv_f2, 1.0f) * sB;
+    const float u = sample_unsigned<Tap, G>(c, tp, inv_f2, scale);
+    return c.fold ? -u : u;
 }
 
 // S_lam at a line's sinogram coordinates.
 template <class Tap, class G>
 __device__ __forceinline__ float sample_at(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec,
                                            float inv_f2, float scale) {
-    const Taps tp = load_taps<Tap, G>(c, sview, ec);
-    const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
-    const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
-    const float B = fmaf(c.fa, r1 - r0, r0);
-    const float sB = Tap::kScaled ? (c.sgn * scale) * B : c.sgn * B;
-    return fmaf(c.tf * c.tf, inv_f2, 1.0f) * sB;
+    return sample_taps<Tap, G>(c, load_taps<Tap, G>(c, sview, ec), inv_f2, scale);
 }
 
 template <class Tap, class G>

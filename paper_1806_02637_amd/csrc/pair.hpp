@@ -25,15 +25,24 @@ __device__ __forceinline__ void pair_from_index(int64_t p, int n, int &a, int &b
     b = (int)(p - pair_index(aa, aa + 1, n)) + aa + 1;
 }
 
-// FP64 per-pair geometry -> the per-plane constants of one pair.
+// FP64 per-pair geometry -> the per-plane constants of one pair.  The line
+// maps come from Eqs. 13-14 (the moved P' of each view), or, when pinv_a /
+// pinv_b are given, from the caller's pseudo-inverses of P' (the route the
+// method replaces; same lines up to a positive scale).
 template <class G>
 __device__ __forceinline__ void pair_setup(const ViewGeom &A, const ViewGeom &Bv, double R_mm, int K,
-                                           PairConst<G> &pc) {
+                                           PairConst<G> &pc, const double *pinv_a = nullptr,
+                                           const double *pinv_b = nullptr) {
     double u1[3], u2[3], km;
     pencil(A.C, Bv.C, R_mm, u1, u2, km);
     double Ha[6], Hb[6];
-    line_map(A.P, A.C, u1, u2, A.u0, A.v0, Ha);
-    line_map(Bv.P, A.C, u1, u2, Bv.u0, Bv.v0, Hb);
+    if (pinv_a) {
+        line_map_pinv(pinv_a, A.C, u1, u2, A.u0, A.v0, Ha);
+        line_map_pinv(pinv_b, A.C, u1, u2, Bv.u0, Bv.v0, Hb);
+    } else {
+        line_map(A.P, A.C, u1, u2, A.u0, A.v0, Ha);
+        line_map(Bv.P, A.C, u1, u2, Bv.u0, Bv.v0, Hb);
+    }
     // (alpha, t) of a line do not change under a positive scale: bring both
     // maps to unit magnitude with an exact power of two
     double ma = 0.0, mb = 0.0;

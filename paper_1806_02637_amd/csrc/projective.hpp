@@ -176,4 +176,22 @@ ECC_HD void line_map(const T Pm[12], const T Ca[3], const T u1[3], const T u2[3]
     }
 }
 
+// The prior route to the same lines: the epipolar plane E maps to its image
+// line through the pseudo-inverse, l = P^{+T} E (P^+ = P^T (P P^T)^{-1},
+// 4x3 row-major); centred about the principal point like line_map.
+template <class T>
+ECC_HD void line_map_pinv(const double Pp[12], const T Ca[3], const T u1[3], const T u2[3], double u0, double v0,
+                          T H[6]) {
+    for (int col = 0; col < 2; ++col) {
+        const T *n = col == 0 ? u1 : u2;
+        T E[4] = {n[0], n[1], n[2], T(0.0) - (n[0] * Ca[0] + n[1] * Ca[1] + n[2] * Ca[2])};
+        T l[3];
+        for (int i = 0; i < 3; ++i)
+            l[i] = T(Pp[i]) * E[0] + T(Pp[3 + i]) * E[1] + T(Pp[6 + i]) * E[2] + T(Pp[9 + i]) * E[3];
+        H[3 * col + 0] = l[0];
+        H[3 * col + 1] = l[1];
+        H[3 * col + 2] = l[2] + l[0] * T(u0) + l[1] * T(v0);
+    }
+}
+
 }  // namespace ecc

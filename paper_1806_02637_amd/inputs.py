@@ -157,8 +157,50 @@ def sphere_phantom(radius_mm: float, density: float = 1.0) -> Phantom:
                    np.array([float(density)]))
 
 
+def rigid_rotation(rx_deg: float, ry_deg: float, rz_deg: float) -> np.ndarray:
+    """R_z R_y R_x of the three angles (degrees), right-handed."""
+    ax, ay, az = np.deg2rad([rx_deg, ry_deg, rz_deg])
+    Rx = np.array([[1, 0, 0], [0, math.cos(ax), -math.sin(ax)], [0, math.sin(ax), math.cos(ax)]])
+    Ry = np.array([[math.cos(ay), 0, math.sin(ay)], [0, 1, 0], [-math.sin(ay), 0, math.cos(ay)]])
+    Rz = np.array([[math.cos(az), -math.sin(az), 0], [math.sin(az), math.cos(az), 0], [0, 0, 1]])
+    return Rz @ Ry @ Rx
+
+
+def moved_frames(geom: ScanGeometry, motion: np.ndarray):
+    """Frames of a scan during which the object moved: the camera of view lam
+    is P T(theta_lam) with T = [[R_z R_y R_x, t], [0, 1]], i.e. rotation
+    R Rm and source Rm^T (C - t)."""
+    C, R = geom.frames()
+    C2, R2 = np.empty_like(C), np.empty_like(R)
+    for i in range(geom.n_views):
+        Rm = rigid_rotation(*motion[i, :3])
+        R2[i] = R[i] @ Rm
+        C2[i] = Rm.T @ (C[i] - motion[i, 3:])
+    return C2, R2
+
+
+def smooth_motion(seed: int, n_views: int, peak: float = 2.0, params=(5,)) -> np.ndarray:
+    """theta [n_views, 6]: for each selected parameter a smooth random curve
+    (three low-frequency sinusoids plus one smooth step, the kind of drift and
+    sudden shift a patient makes), scaled to a peak deviation of ``peak``
+    about its mean; other parameters 0."""
+    rng = np.random.default_rng(seed)
+    lam = np.arange(n_views, dtype=np.float64)
+    th = np.zeros((n_views, 6))
+    for p in params:
+        periods = rng.uniform(n_views / 3.0, 2.0 * n_views, 3)
+        phases = rng.uniform(0.0, 2 * math.pi, 3)
+        amps = rng.normal(size=3)
+        step_at, step_amp = rng.uniform(0.3, 0.7) * n_views, rng.normal()
+        y = sum(a * np.sin(2 * math.pi * lam / T + ph) for a, T, ph in zip(amps, periods, phases))
+        y = y + step_amp * np.tanh((lam - step_at) / (n_views / 20.0))
+        y = y - y.mean()
+        th[:, p] = peak * y / np.abs(y).max()
+    return th
+
+
 def project(geom: ScanGeometry, phantom: Phantom, views=None, device: str = "cpu",
-            chunk_rows: int | None = None, as_tensor: bool = False):
+            chunk_rows: int | None = None, as_tensor: bool = False, motion: np.ndarray | None = None):
     """Analytic line integrals through every pixel centre, FP64, returned FP32.
 
     Returns images [n_sel, H, W] (row v, column u) as a NumPy array, or as an
@@ -167,10 +209,11 @@ def project(geom: ScanGeometry, phantom: Phantom, views=None, device: str = "cpu
     FP64 either way.  For ray X = C + tau * omega (|omega| = 1) and an ellipsoid
     (x_e, a_e, Q_e): y = diag(1/a) Q^T (C - x_e), w = diag(1/a) Q^T omega,
     D = (y.w)^2 - |w|^2 (|y|^2 - 1); the chord length is 2 sqrt(D) / |w|^2 for D > 0.
+    ``motion`` [n_views, 6] projects with the moved cameras of ``moved_frames``.
     """
     import torch
 
-    C_all, R_all = geom.frames()
+    C_all, R_all = geom.frames() if motion is None else moved_frames(geom, np.asarray(motion, dtype=np.float64))
     if views is None:
         views = range(geom.n_views)
     views = list(views)
@@ -274,6 +317,11 @@ WORKLOADS = {
     "adj248": Workload("adj248", ScanGeometry(248, 620, 480, 0.616), 360, 512, 256, 1, 30, 2, 1004,
                        notes="adjoint form: 248 views, K=256, gradient w.r.t. 1488 parameters"),
 }
+
+# motion-estimation experiment (Sec. "Optimization" / "Experiments"): the
+# 496-view scan of an FOV-contained phantom acquired while the object drifts
+# along z (smooth t_z curve, 2 mm peak); the estimate runs on 17 Akima nodes
+MOTION_EXPERIMENT = dict(workload="full496", motion_seed=77, peak_mm=2.0, params=(5,), n_nodes=17)
 
 # served form: 8 scans of uneven view counts; scans with <= 248 views use the
 # 620x480 detector and a 360x512 sinogram with K=256, larger ones 1240x960,
