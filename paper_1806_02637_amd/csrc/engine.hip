@@ -307,7 +307,8 @@ static ecc_status install_sinograms(ecc_ctx *ctx, Scan *s, int32_t n_alpha, int3
     uint64_t tmp_charged = 0;
     float *gw = nullptr, *gwT = nullptr, *ext_tmp = nullptr;
     double *G = nullptr;
-    const uint64_t pad_bytes = sizeof(float) * (uint64_t)s->n_views * (s->W + 2 * kImgPad) * (s->H + 2 * kImgPad);
+    // weighted projections in two orientations, rows stored as interleaved pairs
+    const uint64_t pad_bytes = 2 * sizeof(float) * (uint64_t)s->n_views * (s->W + 2 * kImgPad) * (s->H + 2 * kImgPad);
     const uint64_t G_bytes = sizeof(double) * (uint64_t)s->n_views * n_alpha * n_t;
     const uint64_t ext_bytes = sizeof(float) * (uint64_t)s->n_views * (n_alpha + 1) * n_t;
     auto cleanup = [&]() {

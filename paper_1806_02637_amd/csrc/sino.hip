@@ -3,12 +3,14 @@
 // (Sec. "Epipolar Consistency").
 //
 //  1. sino_weight: radial (cosine) weight f / sqrt(f^2 + x^2 + y^2) on pixel
-//     centres, written twice: row-major and transposed, both with a 3-pixel
-//     zero border so that line samples need no bounds checks.
-//  2. sino_radon: 16 lanes per (view, alpha_m, t_k) cell sum bilinear
-//     samples along its line, only over the stretch where they can be
-//     non-zero; a wave covers 4 neighbouring lines x 16 consecutive samples so
-//     its gathers stay within a small image patch (see the kernel).
+//     centres, written in two orientations (rows = image rows, and rows =
+//     image columns), each with a 3-pixel zero border and with rows stored
+//     in interleaved pairs: element (r, c) holds (row r, row r + 1) at
+//     column c, so one 16-byte load returns a sample's 2 x 2 neighbourhood.
+//  2. sino_radon: a wave sums the bilinear samples of one (view, alpha_m,
+//     t_k) line, its 64 lanes taking consecutive samples, over the stretch
+//     where they can be non-zero; the orientation in which the line runs
+//     along the rows is used, so a wave's gather covers a few cache lines.
 //  3. sino_store: central t-difference of the line integrals, the pad row
 //     at alpha = pi from the odd symmetry, conversion to the storage type and
 //     the row-interleaved layout the consistency kernels read.
@@ -24,9 +26,14 @@ namespace ecc {
 static constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
+// Weighted pixel (x, y) of view v's image is written to both interleaved
+// copies: gw2 (rows = image rows) at (y, x).x and (y - 1, x).y, gwT2 (rows =
+// image columns) at (x, y).x and (x - 1, y).y, all with the 3-pixel border
+// (the buffers are zeroed beforehand).  The transposed writes go through an
+// LDS tile so that both copies are written along their rows.
 __global__ __launch_bounds__(256) void sino_weight_kernel(const float *__restrict__ images,
                                                           const double *__restrict__ intr, int W, int H,
-                                                          float *__restrict__ gw, float *__restrict__ gwT) {
+                                                          float *__restrict__ gw2, float *__restrict__ gwT2) {
     __shared__ float tile[32][33];
     const int v = blockIdx.z;
     const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
@@ -35,22 +42,29 @@ __global__ __launch_bounds__(256) void sino_weight_kernel(const float *__restric
     const float ff = (float)(f * f);
     const float *img = images + (int64_t)v * W * H;
     const int Wp = W + 2 * kImgPad, Hp = H + 2 * kImgPad;
-    float *out = gw + (int64_t)v * Wp * Hp;
-    float *outT = gwT + (int64_t)v * Wp * Hp;
+    // interleaved copies: (Hp - 1) x Wp pairs and (Wp - 1) x Hp pairs
+    float *out = gw2 + (int64_t)v * 2 * Wp * Hp;
+    float *outT = gwT2 + (int64_t)v * 2 * Wp * Hp;
     for (int r = ty; r < 32; r += 8) {
         const int i = i0 + tx, j = j0 + r;
         float val = 0.0f;
         if (i < W && j < H) {
             const float x = (float)(i - u0), y = (float)(j - v0);
             val = img[(int64_t)j * W + i] * ((float)f * rsqrtf(ff + x * x + y * y));
-            out[(int64_t)(j + kImgPad) * Wp + (i + kImgPad)] = val;
+            const int64_t e = (int64_t)(j + kImgPad) * Wp + (i + kImgPad);  // pair index of (row, col)
+            out[2 * e] = val;                 // (row j, col i).x
+            out[2 * (e - Wp) + 1] = val;      // (row j - 1, col i).y
         }
         tile[r][tx] = val;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int i = i0 + r, j = j0 + tx;
-        if (i < W && j < H) outT[(int64_t)(i + kImgPad) * Hp + (j + kImgPad)] = tile[tx][r];
+        if (i < W && j < H) {
+            const int64_t e = (int64_t)(i + kImgPad) * Hp + (j + kImgPad);
+            outT[2 * e] = tile[tx][r];
+            outT[2 * (e - Hp) + 1] = tile[tx][r];
+        }
     }
 }
 
@@ -62,126 +76,131 @@ hipError_t launch_sino_weight(const float *images, const double *intr, int n_vie
 }
 
 // ---------------------------------------------------------------------------
-// s-interval where c0 + s dc stays inside (lo, hi)
-__device__ __forceinline__ void clip_axis(double c0, double dc, double lo, double hi, double &s_lo, double &s_hi) {
-    if (fabs(dc) < 1e-12) {
-        if (!(c0 > lo && c0 < hi)) {
-            s_lo = 1.0;
-            s_hi = -1.0;
-        }
-        return;
-    }
-    double a = (lo - c0) / dc, b = (hi - c0) / dc;
-    if (a > b) {
-        double tmp = a;
-        a = b;
-        b = tmp;
-    }
-    s_lo = fmax(s_lo, a);
-    s_hi = fmin(s_hi, b);
+// s-interval where c0 + s dc stays inside (lo, hi), intersected into
+// [s_lo, s_hi]; dc != 0 is given through its reciprocal.
+__device__ __forceinline__ void clip_axis_r(double c0, double inv_dc, double lo, double hi, double &s_lo,
+                                            double &s_hi) {
+    const double a = (lo - c0) * inv_dc, b = (hi - c0) * inv_dc;
+    s_lo = fmax(s_lo, fmin(a, b));
+    s_hi = fmin(s_hi, fmax(a, b));
 }
 
-typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+// Wave-wide FP64 sum in a fixed order (DPP on both halves: pairs, quads,
+// half rows, rows, then rows 0-1 and 0-3); lane 63 ends with the total,
+// returned to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_f64(double x) {
+    x += dpp_f64<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141, 0xF>(x);  // row_half_mirror
+    x += dpp_f64<0x140, 0xF>(x);  // row_mirror
+    x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15
+    x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
-// Block = 4 waves; wave = 4 detector lines (consecutive t) x 16 lanes along
-// each line.  Lane (ti, si) takes samples j = j0 + si + 16 i of line ti, so
-// one gather of the wave touches a compact patch of about 6 x 8 pixels
-// whatever the angle; the image copy is chosen so that the lines run along
-// its contiguous axis.  Per lane the sample position is kept as an integer
-// pixel plus an FP32 fraction renormalised every step (drift < 1e-4 px over
-// a line); per-lane sums are flushed from FP32 to FP64 every 32 steps and the
-// 16 lane sums of a line are added in a fixed butterfly order.
-__global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict__ gw, const float *__restrict__ gwT,
+typedef float f32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+// Block = 4 waves; each wave sums kLinesPerWave consecutive lines (t_k) of
+// one alpha_m, one after the other.  For a line, lane l takes the samples
+// j = j_lo + l + 64 i of its clipped stretch [j_lo, j_hi]; positions are
+// carried in FP64 (one add per sample and axis, no drift), the pad offset
+// included so that they stay positive and truncation is the floor.  Each
+// lane sums up to 32 samples in FP32 before adding to its FP64 total; the 64
+// lane totals are added in a fixed butterfly order.
+constexpr int kLinesPerWave = 4;
+
+__global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict__ gw2,
+                                                         const float *__restrict__ gwT2,
                                                          const double *__restrict__ intr, int W, int H,
                                                          int n_alpha, int n_t, double t_max, double dt, double ds,
                                                          int n_s, double *__restrict__ G) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ti = lane >> 4, si = lane & 15;
-    const int k = (blockIdx.x * 4 + wave) * 4 + ti;
     const int m = blockIdx.y, v = blockIdx.z;
     const double u0 = intr[3 * v + 1], v0 = intr[3 * v + 2];
     const double alpha = m * (kPi / n_alpha);
     double sa, ca;
     sincos(alpha, &sa, &ca);
-    const double t = -t_max + (k < n_t ? k : 0) * dt;
-    // sample at s: (x, y) = (u0 + t ca - s sa, v0 + t sa + s ca); the line
-    // direction (-sa, ca) is closer to the x axis when |sa| > |ca|
+    // sample at s: (x, y) = (u0 + t ca - s sa, v0 + t sa + s ca); use the copy
+    // whose rows run closer to the line direction (-sa, ca)
     const bool trans = fabs(sa) <= fabs(ca);  // uniform over the block
-    double p0, q0, dp, dq;
-    int P_ext, Q_ext;
-    const float *img;
-    if (!trans) {
-        p0 = u0 + t * ca;
-        q0 = v0 + t * sa;
-        dp = -sa;
-        dq = ca;
-        P_ext = W;
-        Q_ext = H;
-        img = gw + (int64_t)v * (W + 2 * kImgPad) * (H + 2 * kImgPad);
-    } else {
-        p0 = v0 + t * sa;
-        q0 = u0 + t * ca;
-        dp = ca;
-        dq = -sa;
-        P_ext = H;
-        Q_ext = W;
-        img = gwT + (int64_t)v * (W + 2 * kImgPad) * (H + 2 * kImgPad);
-    }
-    const int pitch = P_ext + 2 * kImgPad;
-    double s_lo = -1e300, s_hi = 1e300;
-    clip_axis(p0, dp, -1.0, (double)P_ext, s_lo, s_hi);
-    clip_axis(q0, dq, -1.0, (double)Q_ext, s_lo, s_hi);
+    const int Wp = W + 2 * kImgPad, Hp = H + 2 * kImgPad;
+    const int P_ext = trans ? H : W, Q_ext = trans ? W : H;
+    const int pitch = trans ? Hp : Wp;  // pairs per row
+    const double dp = trans ? ca : -sa, dq = trans ? -sa : ca;
+    const float *img = (trans ? gwT2 : gw2) + (int64_t)v * 2 * Wp * Hp;
     const double c = 0.5 * (n_s - 1);
-    int j_lo = 1, j_hi = 0;  // empty
-    if (k < n_t && s_lo <= s_hi) {
-        // one extra sample (ds <= 1 px) on each side absorbs rounding of the
-        // clip: samples stay within 2 px of the image, inside the zero border
-        j_lo = max(0, (int)ceil(s_lo / ds + c) - 1);
-        j_hi = min(n_s - 1, (int)floor(s_hi / ds + c) + 1);
-    }
-    // wave-uniform sweep over the union of the four lines' ranges
-    int w_lo = j_lo <= j_hi ? j_lo : 0x7fffffff, w_hi = j_lo <= j_hi ? j_hi : -1;
-    for (int off = 16; off < 64; off <<= 1) {
-        w_lo = min(w_lo, __shfl_xor(w_lo, off, 64));
-        w_hi = max(w_hi, __shfl_xor(w_hi, off, 64));
-    }
-    double acc = 0.0;
-    if (w_lo <= w_hi) {
-        const int j_first = w_lo + si;
-        const double s = (j_first - c) * ds;
-        const double pp = p0 + s * dp, qq = q0 + s * dq;
-        const double pfl = floor(pp), qfl = floor(qq);
-        float fp = (float)(pp - pfl), fq = (float)(qq - qfl);
-        int ip = (int)pfl + kImgPad, iq = (int)qfl + kImgPad;
-        const float sp = (float)(16.0 * ds * dp), sq = (float)(16.0 * ds * dq);
-        float part = 0.0f;
-        int n_in_part = 0;
-        for (int j = j_first; j - si <= w_hi; j += 16) {
-            if (j >= j_lo && j <= j_hi) {
-                const float *ptr = img + (int64_t)iq * pitch + ip;
-                const float2_a4 top = *(const float2_a4 *)ptr;
-                const float2_a4 bot = *(const float2_a4 *)(ptr + pitch);
-                const float a = fmaf(fp, top.y - top.x, top.x);
-                const float b = fmaf(fp, bot.y - bot.x, bot.x);
-                part += fmaf(fq, b - a, a);
+    const double step_p = 64.0 * ds * dp, step_q = 64.0 * ds * dq;
+    // reciprocals for the clip: |dp| >= 1/sqrt(2) by the choice of copy, dq
+    // may vanish (lines along an image axis)
+    const double inv_dp = 1.0 / dp, inv_ds = 1.0 / ds;
+    const bool q_flat = fabs(dq) < 1e-12;
+    const double inv_dq = q_flat ? 0.0 : 1.0 / dq;
+    for (int li = 0; li < kLinesPerWave; ++li) {
+        const int k = (blockIdx.x * 4 + wave) * kLinesPerWave + li;
+        if (k >= n_t) break;  // wave-uniform
+        const double t = -t_max + k * dt;
+        const double p0 = trans ? v0 + t * sa : u0 + t * ca;
+        const double q0 = trans ? u0 + t * ca : v0 + t * sa;
+        double s_lo = -1e300, s_hi = 1e300;
+        clip_axis_r(p0, inv_dp, -1.0, (double)P_ext, s_lo, s_hi);
+        if (q_flat) {
+            if (!(q0 > -1.0 && q0 < (double)Q_ext)) {
+                s_lo = 1.0;
+                s_hi = -1.0;
             }
-            fp += sp;
-            fq += sq;
-            const float flp = floorf(fp), flq = floorf(fq);
-            fp -= flp;
-            fq -= flq;
-            ip += (int)flp;
-            iq += (int)flq;
-            if (++n_in_part == 32) {
-                acc += (double)part;
-                part = 0.0f;
-                n_in_part = 0;
-            }
+        } else {
+            clip_axis_r(q0, inv_dq, -1.0, (double)Q_ext, s_lo, s_hi);
         }
-        acc += (double)part;
+        int n = 0, j_lo = 0;
+        if (s_lo <= s_hi) {
+            // one extra sample (ds <= 1 px) on each side absorbs rounding of
+            // the clip: samples stay within 2 px of the image, inside the
+            // zero border
+            j_lo = max(0, (int)ceil(s_lo * inv_ds + c) - 1);
+            n = min(n_s - 1, (int)floor(s_hi * inv_ds + c) + 1) - j_lo + 1;
+        }
+        n = __builtin_amdgcn_readfirstlane(max(n, 0));  // the same on every lane
+        const double s = (j_lo + lane - c) * ds;
+        double pp = p0 + s * dp + kImgPad, qq = q0 + s * dq + kImgPad;
+        auto sample = [&]() {
+            // positions are positive: truncation is the floor, and the
+            // hardware fraction is pp - floor(pp)
+            const int ip = (int)pp, iq = (int)qq;
+            const float fp = (float)__builtin_amdgcn_fract(pp), fq = (float)__builtin_amdgcn_fract(qq);
+            const uint32_t e = __umul24((uint32_t)iq, (uint32_t)pitch) + (uint32_t)ip;
+            const f32x4_a8 g = *(const f32x4_a8 *)((const char *)img + e * 8u);
+            // g = (row iq, row iq + 1) at column ip, then at column ip + 1
+            const float a = fmaf(fp, g.z - g.x, g.x);
+            const float b = fmaf(fp, g.w - g.y, g.y);
+            return fmaf(fq, b - a, a);
+        };
+        double acc = 0.0;
+        const int n_full = n >> 6;  // sweeps in which every lane has a sample (wave-uniform)
+        for (int i0 = 0; i0 < n_full; i0 += 32) {
+            const int i1 = min(i0 + 32, n_full);
+            float part = 0.0f;
+#pragma unroll 4
+            for (int i = i0; i < i1; ++i) {
+                part += sample();
+                pp += step_p;
+                qq += step_q;
+            }
+            acc += (double)part;
+        }
+        if (lane < (n & 63)) acc += (double)sample();
+        acc = wave_sum_f64(acc);
+        if (lane == 0) G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
     }
-    for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
-    if (si == 0 && k < n_t) G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
 }
 
 hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *intr, int n_views, int W, int H,
@@ -189,7 +208,7 @@ hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *in
     const double t_max = 0.5 * sqrt((double)W * W + (double)H * H);
     const double dt = 2.0 * t_max / (n_t - 1);
     const int n_s = 2 * (int)ceil(t_max / ds) + 1;
-    dim3 grid((n_t + 15) / 16, n_alpha, n_views);  // 16 lines per block
+    dim3 grid((n_t + 4 * kLinesPerWave - 1) / (4 * kLinesPerWave), n_alpha, n_views);
     hipLaunchKernelGGL(sino_radon_kernel, grid, dim3(256), 0, s, gw, gwT, intr, W, H, n_alpha, n_t, t_max, dt, ds,
                        n_s, G);
     return hipGetLastError();
