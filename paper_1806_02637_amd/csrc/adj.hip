@@ -98,6 +98,12 @@ __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const View
     return ldexp(ga, -ea) + ldexp(gb, -eb) + (double)g13[12] * km.d;
 }
 
+// Cost and the pair sensitivities in one sweep over the planes.  With
+// d = sum (S_a - S_b)^2 / N, e = d / (1 + d / c), every plane's gradient
+// term is (2 / (N den^2)) (S_a - S_b) d(S_a - S_b), den = 1 + d / c: the
+// factor in front is one number per pair, so the sweep accumulates
+// (S_a - S_b) d(S_a - S_b) alongside the cost and the factor is applied
+// after the wave sums (no second sweep re-deriving the lines).
 template <class Tap, class G>
 __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ sino,
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
@@ -117,6 +123,10 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
 
     const Tap *base = (const Tap *)sino;
     const float kinv = 1.0f / (float)ec.K;
+    const bool has_tail = (ec.K & 63) != 0;
+    const int n_sweeps = (ec.K >> 6) + (has_tail ? 1 : 0);
+    const bool in_tail = lane < (ec.K & 63);
+    const uint64_t tail_mask = (1ull << (ec.K & 63)) - 1;
     double wave_acc = 0.0;
     for (int q = 0; q < kPairsPerWave; ++q) {
         const PairConst<G> pc = uniform(slots[wave][q]);
@@ -124,59 +134,41 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         const int64_t p = pair_index(pc.va, pc.vb, ec.n_views);
         const Tap *sa = base + (int64_t)pc.va * ec.view_elems;
         const Tap *sb = base + (int64_t)pc.vb * ec.view_elems;
-        // 1. forward sweep
         float acc = 0.0f;
         int cnt = 0;
-        G sn0, cs0;
-        g_sincos(pc.k0 + (G)lane * pc.dk, &sn0, &cs0);
-        G sn = sn0, cs = cs0;
-        for (int k = lane; k < ec.K; k += 64) {
-            bool ha, hb;
-            const float Sa = lookup<Tap, G>(pc.ha, cs, sn, sa, ec, pc.inv_f2a, pc.sa, ha);
-            const float Sb = lookup<Tap, G>(pc.hb, cs, sn, sb, ec, pc.inv_f2b, pc.sb, hb);
-            if (ha && hb) {
-                const float diff = Sa - Sb;
+        float g[13];
+        for (int i = 0; i < 13; ++i) g[i] = 0.0f;
+        G sn, cs;
+        g_sincos(pc.k0 + (G)lane * pc.dk, &sn, &cs);
+        for (int i = 0; i < n_sweeps; ++i) {
+            const bool last = has_tail & (i == n_sweeps - 1);
+            const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
+            const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
+            const Taps ta = load_taps<Tap, G>(ca, sa, ec);
+            const Taps tb = load_taps<Tap, G>(cb, sb, ec);
+            const bool hit = (!last | in_tail) & ca.hit & cb.hit;
+            cnt += __popcll(hit_mask(ca) & hit_mask(cb) & (last ? tail_mask : ~0ull));
+            if (hit) {
+                const float diff = sample_taps<Tap, G>(ca, ta, pc.inv_f2a, pc.sa) -
+                                   sample_taps<Tap, G>(cb, tb, pc.inv_f2b, pc.sb);
                 acc = fmaf(diff, diff, acc);
-                ++cnt;
+                float gk = 0.0f;
+                lookup_adjoint<Tap, G>(pc.ha, cs, sn, ta, ec, pc.inv_f2a, pc.sa, diff, ca, g, gk);
+                lookup_adjoint<Tap, G>(pc.hb, cs, sn, tb, ec, pc.inv_f2b, pc.sb, -diff, cb, g + 6, gk);
+                // kappa_k = kappa_max ((2k + 1) / K - 1), k = lane + 64 i
+                g[12] = fmaf(gk, (float)(2 * (lane + 64 * i) + 1) * kinv - 1.0f, g[12]);
             }
             const G c2 = cs * pc.rc - sn * pc.rs;
             sn = sn * pc.rc + cs * pc.rs;
             cs = c2;
         }
         acc = wave_sum(acc);
-        cnt = wave_sum_i(cnt);
         const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
         const float den = 1.0f + d * ec.inv_c;
         const float e = ec.inv_c > 0.0f ? d / den : d;
         wave_acc += (double)e;
-        float g[13];
-        for (int i = 0; i < 13; ++i) g[i] = 0.0f;
-        if (cnt > 0) {
-            // 2. reverse sweep
-            const float coef = 2.0f / ((float)cnt * den * den);
-            sn = sn0;
-            cs = cs0;
-            for (int k = lane; k < ec.K; k += 64) {
-                const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
-                const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
-                if (ca.hit && cb.hit) {
-                    const Taps ta = load_taps<Tap, G>(ca, sa, ec);
-                    const Taps tb = load_taps<Tap, G>(cb, sb, ec);
-                    const float Sa = sample_taps<Tap, G>(ca, ta, pc.inv_f2a, pc.sa);
-                    const float Sb = sample_taps<Tap, G>(cb, tb, pc.inv_f2b, pc.sb);
-                    const float gS = coef * (Sa - Sb);
-                    float gk = 0.0f;
-                    lookup_adjoint<Tap, G>(pc.ha, cs, sn, ta, ec, pc.inv_f2a, pc.sa, gS, ca, g, gk);
-                    lookup_adjoint<Tap, G>(pc.hb, cs, sn, tb, ec, pc.inv_f2b, pc.sb, -gS, cb, g + 6, gk);
-                    // kappa_k = kappa_max ((2k + 1) / K - 1)
-                    g[12] = fmaf(gk, (float)(2 * k + 1) * kinv - 1.0f, g[12]);
-                }
-                const G c2 = cs * pc.rc - sn * pc.rs;
-                sn = sn * pc.rc + cs * pc.rs;
-                cs = c2;
-            }
-            for (int i = 0; i < 13; ++i) g[i] = wave_sum(g[i]);
-        }
+        const float coef = cnt > 0 ? 2.0f / ((float)cnt * den * den) : 0.0f;
+        for (int i = 0; i < 13; ++i) g[i] = coef * wave_sum(g[i]);
         if (lane == 0) {
             float *out = sens + ((int64_t)hyp * ec.n_pairs + p) * 13;
             for (int i = 0; i < 13; ++i) out[i] = g[i];

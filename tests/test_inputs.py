@@ -63,3 +63,17 @@ def test_workload_table():
     assert abs(inputs.WORKLOADS["small16"].R_mm - 94.68) < 0.01
     assert abs(inputs.WORKLOADS["mid248"].R_mm - 91.19) < 0.01
     assert [s.geom.n_views for s in inputs.serve_workloads()] == list(inputs.SERVE_VIEW_COUNTS)
+
+
+def test_smooth_motion_recipe():
+    from paper_1806_02637_amd import inputs
+
+    th = inputs.smooth_motion(77, 496, peak=2.0, params=(5,))
+    assert th.shape == (496, 6)
+    assert np.all(th[:, :5] == 0.0)
+    assert abs(th[:, 5].mean()) < 1e-12 and abs(np.abs(th[:, 5]).max() - 2.0) < 1e-12
+    # smooth: view-to-view steps far below the peak
+    assert np.abs(np.diff(th[:, 5])).max() < 0.1
+    np.testing.assert_array_equal(th, inputs.smooth_motion(77, 496, peak=2.0, params=(5,)))
+    two = inputs.smooth_motion(3, 100, peak=1.0, params=(0, 4))
+    assert np.all(two[:, [1, 2, 3, 5]] == 0.0) and np.all(np.abs(two[:, [0, 4]]).max(axis=0) > 0.999)
