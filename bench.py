@@ -300,9 +300,10 @@ def measure_motion_estimation(eng, max_iter=60):
 def measure_serving(eng, n_requests=48, seed=7, load=0.8):
     """Served form: 8 resident scans of uneven view counts, Poisson arrivals of
     64-hypothesis requests (half cost+gradient).  The same trace is served (a)
-    with BF16 sinograms by the continuous-batching server (4 slots) and (b)
-    serially with plain FP32 sinograms (1 slot); the arrival rate is `load`
-    times the serial FP32 capacity."""
+    with BF16 sinograms by the continuous-batching server (4 slots, work in
+    flight capped at 1.5 x the largest request, gradients counted twice) and
+    (b) serially with plain FP32 sinograms (1 slot); the arrival rate is
+    `load` times the serial FP32 capacity."""
     import torch
 
     from paper_1806_02637_amd import inputs
@@ -326,6 +327,8 @@ def measure_serving(eng, n_requests=48, seed=7, load=0.8):
         wl = wls[j]
         reqs.append((j, inputs.random_motion(int(rng.integers(1 << 30)), wl.B, wl.geom.n_views), bool(i % 2)))
     evals = sum(wls[j].B * wls[j].n_pairs * wls[j].K for j, _, _ in reqs)
+    work_cap = 1.5 * max(2.0 * wl.B * wl.n_pairs * wl.K for wl in wls)
+    caps = {1: 0.0, 4: work_cap}
 
     def trace(kind, arrivals):
         return [(float(arrivals[i]), scans[kind][j], th, wls[j].K, wls[j].R_mm, g)
@@ -335,7 +338,7 @@ def measure_serving(eng, n_requests=48, seed=7, load=0.8):
     # also sets the capacity the Poisson rate is scaled to
     burst = {}
     for name, kind, slots in (("serial_f32", "f32", 1), ("served_bf16", "bf16", 4)):
-        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30)
+        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30, work_cap=caps[slots])
         _, span = replay(srv, trace(kind, np.zeros(n_requests)))
         srv.close()
         burst[name] = {"makespan_s": span, "evals_per_s": evals / span, "slots": slots}
@@ -344,9 +347,9 @@ def measure_serving(eng, n_requests=48, seed=7, load=0.8):
     arrivals = poisson_arrivals(rate, n_requests, seed)
     out = {"requests": n_requests, "arrival_rate_per_s": rate, "load_vs_serial_f32_capacity": load,
            "scans_views": [wl.geom.n_views for wl in wls], "hypotheses_per_request": 64, "grad_fraction": 0.5,
-           "burst": burst}
+           "served_work_cap": work_cap, "burst": burst}
     for name, kind, slots in (("served_bf16", "bf16", 4), ("serial_f32", "f32", 1)):
-        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30)
+        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30, work_cap=caps[slots])
         res, makespan = replay(srv, trace(kind, arrivals))
         srv.close()
         lat = latency_summary(res)

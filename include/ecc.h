@@ -244,6 +244,15 @@ ecc_status ecc_server_wait(ecc_server *srv, int64_t request_id, double *cost_hos
 ecc_status ecc_server_request_bytes(ecc_server *srv, int32_t scan_id, int32_t B, int32_t with_grad,
                                     uint64_t *bytes);
 
+/* Caps the work in flight: the head of the queue is admitted only while the
+ * plane-pair evaluations of the running requests plus its own (B x pairs x
+ * K, gradient requests counted twice) stay within work_cap, or when nothing
+ * runs.  A large request then shares the device with small ones only, which
+ * bounds the tail latency that sharing adds.  0 (the default) = admission by
+ * free slot and arena only.  Applies to later admissions.  Errors: ECC_E_ARG
+ * (NULL server, negative or non-finite cap). */
+ecc_status ecc_server_set_work_cap(ecc_server *srv, double work_cap);
+
 /* Stops the worker after the requests already admitted finish, fails the
  * queued ones, and frees the server's streams and arenas. */
 ecc_status ecc_server_destroy(ecc_server *srv);

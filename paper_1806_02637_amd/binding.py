@@ -25,7 +25,7 @@ SYMBOLS = (
     "ecc_scan_set_sinograms", "ecc_scan_read_sinogram", "ecc_scan_free", "ecc_scan_bytes", "ecc_workspace_bytes",
     "ecc_cost", "ecc_cost_grad", "ecc_cost_pinv", "ecc_scan_info", "ecc_spline_motion", "ecc_spline_motion_grad",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_wait", "ecc_server_request_bytes",
-    "ecc_server_destroy",
+    "ecc_server_set_work_cap", "ecc_server_destroy",
 )
 
 
@@ -72,6 +72,7 @@ _SIGNATURES = {
     "ecc_server_poll": ([_P, ctypes.c_int64, ctypes.POINTER(_I32)], _I32),
     "ecc_server_wait": ([_P, ctypes.c_int64, _P, _P, ctypes.POINTER(RequestStats)], _I32),
     "ecc_server_request_bytes": ([_P, _I32, _I32, _I32, ctypes.POINTER(_U64)], _I32),
+    "ecc_server_set_work_cap": ([_P, ctypes.c_double], _I32),
     "ecc_server_destroy": ([_P], _I32),
 }
 
@@ -212,6 +213,10 @@ def ecc_server_wait(srv: int, request_id: int, cost_host_ptr: int, grad_host_ptr
     _check(load_library().ecc_server_wait(srv, request_id, cost_host_ptr, grad_host_ptr, ctypes.byref(st)),
            "ecc_server_wait")
     return st
+
+
+def ecc_server_set_work_cap(srv: int, work_cap: float):
+    _check(load_library().ecc_server_set_work_cap(srv, float(work_cap)), "ecc_server_set_work_cap")
 
 
 def ecc_server_request_bytes(srv: int, scan_id: int, B: int, with_grad: int) -> int:

@@ -272,19 +272,4 @@ __device__ __forceinline__ float sample_taps(const LineCoord<G> &c, const Taps &
     return c.fold ? -u : u;
 }
 
-// S_lam at a line's sinogram coordinates.
-template <class Tap, class G>
-__device__ __forceinline__ float sample_at(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec,
-                                           float inv_f2, float scale) {
-    return sample_taps<Tap, G>(c, load_taps<Tap, G>(c, sview, ec), inv_f2, scale);
-}
-
-template <class Tap, class G>
-__device__ __forceinline__ float lookup(const G h[6], G cs, G sn, const Tap *sview, const EvalConsts &ec,
-                                        float inv_f2, float scale, bool &hit) {
-    const LineCoord<G> c = line_coord<G>(h, cs, sn, ec);
-    hit = c.hit;
-    return sample_at<Tap, G>(c, sview, ec, inv_f2, scale);
-}
-
 }  // namespace ecc

@@ -82,15 +82,6 @@ __device__ __forceinline__ float wave_sum(float x) {
     x += __int_as_float(dpp_i<0x143, 0xC>(__float_as_int(x)));  // row_bcast:31
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
-__device__ __forceinline__ int wave_sum_i(int x) {
-    x += dpp_i<0xB1, 0xF>(x);
-    x += dpp_i<0x4E, 0xF>(x);
-    x += dpp_i<0x141, 0xF>(x);
-    x += dpp_i<0x140, 0xF>(x);
-    x += dpp_i<0x142, 0xA>(x);
-    x += dpp_i<0x143, 0xC>(x);
-    return __builtin_amdgcn_readlane(x, 63);
-}
 
 // Pair tiles: the views are cut into blocks of kViewBlock consecutive views and
 // a tile is one (block I, block J >= I) product -- up to 8 x 8 pairs (I < J)

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -95,6 +96,7 @@ struct Request {
     int slot = -1, ran_slot = -1;
     uint64_t dev_off = 0, dev_bytes = 0, host_off = 0, host_bytes = 0;
     uint64_t ws_bytes = 0;
+    double work = 0.0;  // plane-pair evaluations, a gradient counted twice
     hipEvent_t done_ev = nullptr;
 };
 
@@ -112,6 +114,8 @@ struct ecc_server {
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> pending;
     std::vector<Request *> running;
+    double work_cap = 0.0;       // 0: none
+    double work_in_flight = 0.0;
     std::map<int64_t, std::unique_ptr<Request>> requests;
     int64_t next_id = 1;
     bool stop = false;
@@ -185,6 +189,8 @@ void launch(ecc_server *s, Request *r, const Layout &L) {
 
 void release(ecc_server *s, Request *r) {
     if (r->slot >= 0) {
+        s->work_in_flight -= r->work;
+        if (s->work_in_flight < 0.5) s->work_in_flight = 0.0;
         s->slot_busy[r->slot] = false;
         s->dev_alloc.release(r->dev_off, r->dev_bytes);
         s->host_alloc.release(r->host_off, r->host_bytes);
@@ -229,6 +235,9 @@ void worker_loop(ecc_server *s) {
                     break;
                 }
             if (slot < 0) break;
+            // with a work cap, an admitted request must fit under it together
+            // with the work in flight (an idle device always takes the head)
+            if (s->work_cap > 0.0 && !s->running.empty() && s->work_in_flight + r->work > s->work_cap) break;
             uint64_t ws = 0;
             const ecc_status wsst = ecc_workspace_bytes(s->ctx, r->scan, r->B, r->with_grad, &ws);
             if (wsst != ECC_OK) {
@@ -260,6 +269,7 @@ void worker_loop(ecc_server *s) {
             r->host_off = hoff;
             r->host_bytes = L.host_total;
             r->t_admit = clk::now();
+            s->work_in_flight += r->work;
             launch(s, r, L);
             if (r->state == RUNNING) {
                 s->running.push_back(r);
@@ -344,6 +354,7 @@ ecc_status ecc_server_submit(ecc_server *s, int32_t scan_id, int32_t B, const do
     r->n_views = n_views;
     r->with_grad = with_grad != 0;
     r->prm = *params;
+    r->work = (double)B * ((double)n_views * (n_views - 1) / 2) * params->K * (with_grad ? 2.0 : 1.0);
     r->theta.assign(theta_host, theta_host + 6ull * B * n_views);
     r->cost.assign(B, 0.0);
     if (r->with_grad) r->grad.assign(6ull * B * n_views, 0.0f);
@@ -418,6 +429,15 @@ ecc_status ecc_server_request_bytes(ecc_server *s, int32_t scan_id, int32_t B, i
     uint64_t ws = 0;
     if ((st = ecc_workspace_bytes(s->ctx, scan_id, B, with_grad, &ws)) != ECC_OK) return st;
     *bytes = align256(request_layout(B, n_views, with_grad, ws).dev_total);
+    return ECC_OK;
+}
+
+ecc_status ecc_server_set_work_cap(ecc_server *s, double work_cap) {
+    if (!s) return set_err(ECC_E_ARG, "null server");
+    if (!(work_cap >= 0.0) || !std::isfinite(work_cap)) return set_err(ECC_E_ARG, "work cap must be finite and >= 0");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->work_cap = work_cap;
+    s->cv_work.notify_all();
     return ECC_OK;
 }
 

@@ -27,9 +27,11 @@ class Result:
 
 
 class Server:
-    def __init__(self, engine, n_slots: int = 4, arena_bytes: int = 8 << 30):
+    def __init__(self, engine, n_slots: int = 4, arena_bytes: int = 8 << 30, work_cap: float = 0.0):
         self.engine = engine
         self.srv = B.ecc_server_create(engine.ctx, n_slots, arena_bytes)
+        if work_cap:
+            B.ecc_server_set_work_cap(self.srv, work_cap)
         self._meta = {}
         self._lock = threading.Lock()
 

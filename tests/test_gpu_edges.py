@@ -1,0 +1,94 @@
+"""Edge cases of the cost against the FP64 oracle (oracle sinograms, so only
+geometry, lookup and reduction are compared): the smallest scan (two views,
+one pair), the largest plane count K = 4096, a view moved far enough that
+many planes miss a detector, and a finite Cauchy constant small enough to
+saturate."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.ecc import as_rows, ecc_pair, pair_index
+from paper_1806_02637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+
+    from paper_1806_02637_amd import engine
+
+    assert torch.cuda.is_available()
+    e = engine.Engine(0)
+    yield e
+    e.close()
+
+
+def _scan(eng, n_views, seed):
+    g = inputs.ScanGeometry(n_views, 128, 128, 2.4)
+    P, intr = g.projection_matrices(), g.intrinsics()
+    imgs = inputs.project(g, inputs.random_phantom(seed, 10))
+    grid = oracle.SinoGrid(g.W, g.H, 180, 181, 0.5)
+    sino = oracle.FullSinograms.build(imgs, grid, intr)
+    scan = eng.load_scan(P, intr, imgs)
+    scan.set_sinograms(sino.data.astype(np.float32), "f32")
+    return g, P, intr, grid, sino, scan
+
+
+def test_two_views_and_max_planes(eng):
+    """With two views the cost is one pair's e, so the per-pair bar applies
+    (2e-4 relative: e is a mean of squared differences of nearly equal
+    values, and with K = 1 a single plane's difference, so the FP32 error of
+    S is amplified by |S| / |S_a - S_b|)."""
+    _say("case: edges two views, K in (1, 64, 4096)")
+    g, P, intr, grid, sino, scan = _scan(eng, 2, 7)
+    th = inputs.random_motion(5, 3, 2)
+    for K in (1, 64, 4096):
+        params = oracle.EccParams(K, g.default_object_radius())
+        got = scan.cost(th, K, params.R_mm).cpu().numpy()
+        for h in range(3):
+            ref = oracle.ecc_cost(P, intr, th[h], grid, sino, params)[0]
+            _say(f"  K={K} hyp {h}: {got[h]:.6e} vs {ref:.6e}")
+            assert abs(got[h] - ref) <= 2e-4 * abs(ref) + 1e-9
+    scan.free()
+
+
+def test_view_moved_far_partial_hits(eng):
+    """One view lifted 60 mm along the rotation axis: many of its planes'
+    lines leave one of the two detectors, so N < K and the hit test decides
+    which planes count (the reading of Eq. 15's N)."""
+    _say("case: edges one view moved 60 mm (partial hits)")
+    g, P, intr, grid, sino, scan = _scan(eng, 6, 8)
+    th = np.zeros((1, 6, 6))
+    th[0, 2, 5] = 60.0
+    params = oracle.EccParams(64, g.default_object_radius())
+    cost, pairs = scan.cost(th, 64, params.R_mm, with_pairs=True)
+    cost, pairs = float(cost.cpu()[0]), pairs.cpu().numpy()[0]
+    for a in range(6):
+        for b in range(a + 1, 6):
+            e_ref = ecc_pair(as_rows(P[a]), as_rows(P[b]), list(th[0, a]), list(th[0, b]), intr[a], intr[b], grid,
+                             sino, a, b, params)[0]
+            e = pairs[pair_index(a, b, 6)]
+            assert abs(e - e_ref) <= 2e-4 * e_ref + 1e-5 * pairs.max(), (a, b, e, e_ref)
+    ref = oracle.ecc_cost(P, intr, th[0], grid, sino, params)[0]
+    assert abs(cost - ref) <= 1e-5 * ref
+    scan.free()
+
+
+def test_saturating_cauchy(eng):
+    _say("case: edges Cauchy c far below d (e -> c)")
+    g, P, intr, grid, sino, scan = _scan(eng, 5, 9)
+    th = inputs.random_motion(6, 2, 5)
+    c = 1e-3
+    params = oracle.EccParams(64, g.default_object_radius(), c)
+    got = scan.cost(th, 64, params.R_mm, c).cpu().numpy()
+    for h in range(2):
+        ref = oracle.ecc_cost(P, intr, th[h], grid, sino, params)[0]
+        assert abs(got[h] - ref) <= 1e-5 * ref
+        assert ref <= 10 * c + 1e-12  # 10 pairs, each e < c
+    scan.free()

@@ -151,3 +151,34 @@ def test_freed_scan_fails_queued_requests(served):
             failed += 1
     assert ok + failed == 30 and failed >= 1
     srv.close()
+
+
+def test_work_cap_admission(served):
+    from paper_1806_02637_amd.serve import Server
+
+    _say("case: serve work cap")
+    eng, scans = served
+    sc, g, K, R = scans[2]
+    work = 8 * (g.n_views * (g.n_views - 1) // 2) * K * 2  # gradient requests count twice
+    th = inputs.random_motion(13, 8, g.n_views)
+    ref = None
+    for cap, most in ((work, 1), (2 * work, 2)):
+        srv = Server(eng, n_slots=4, arena_bytes=1 << 30, work_cap=cap)
+        t_sub, ids = [], []
+        for _ in range(8):
+            t_sub.append(time.perf_counter())
+            ids.append(srv.submit(sc, th, K, R, with_grad=True))
+        res = [srv.wait(i) for i in ids]
+        iv = [(t + r.queue_ms * 1e-3, t + r.total_ms * 1e-3) for t, r in zip(t_sub, res)]
+        # admissions happen only after a completion frees enough work
+        overlap = max(sum(1 for a, b in iv if a + 2e-4 <= x < b - 2e-4) for x, _ in iv)
+        assert overlap <= most, (cap, overlap)
+        ref = res[0].cost if ref is None else ref
+        for r in res:
+            assert np.array_equal(r.cost, ref)
+        srv.close()
+    srv = Server(eng, n_slots=2, arena_bytes=1 << 24)
+    with pytest.raises(binding.EccError) as ei:
+        binding.ecc_server_set_work_cap(srv.srv, -1.0)
+    assert ei.value.status == binding.ECC_E_ARG
+    srv.close()
