@@ -157,14 +157,18 @@ def cpu_baseline(w, imgs_dev, P, intr, thetas, target_s=12.0, n_views=12, n_hyp=
     pairs = [(a, b) for i, a in enumerate(views) for b in views[i + 1:]]
     n_h = min(n_hyp, len(thetas))
 
-    def run():
+    ref = {}
+
+    def run(record=False):
         for h in range(n_h):
             for a, b in pairs:
-                ecc_pair(as_rows(P[a]), as_rows(P[b]), list(thetas[h][a]), list(thetas[h][b]), intr[a], intr[b],
-                         grid, lazy, a, b, params)
+                e = ecc_pair(as_rows(P[a]), as_rows(P[b]), list(thetas[h][a]), list(thetas[h][b]), intr[a], intr[b],
+                             grid, lazy, a, b, params)[0]
+                if record:
+                    ref[(h, a, b)] = float(e)
 
     t0 = time.perf_counter()
-    run()  # fills the touched cells
+    run(record=True)  # fills the touched cells and keeps the oracle's e
     fill = time.perf_counter() - t0
     _log(f"oracle: sample cells filled in {fill:.1f} s")
     dt, passes = 0.0, 0
@@ -179,6 +183,7 @@ def cpu_baseline(w, imgs_dev, P, intr, thetas, target_s=12.0, n_views=12, n_hyp=
            "sample": f"{len(pairs)} pairs among {n_views} seeded views x {n_h} hypotheses x K={w.K}, "
                      f"evaluated {passes} times ({evals} evals in {dt:.1f} s; an untimed first pass "
                      f"filled the touched sinogram cells in {fill:.1f} s)"}
+    out["_oracle_e"] = ref  # consumed by the oracle check, not printed
     n_proc = min(16, os.cpu_count() or 1)
     if n_proc > 1:
         try:
@@ -204,9 +209,10 @@ def timed(fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps):
+def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps, pairs_out, n_check=8):
     """Precision forms and the adjoint on the same workload, each against the
-    plain FP32 step (same GPU, same inputs)."""
+    plain FP32 step (same GPU, same inputs).  pairs_out[name] receives the
+    per-pair e of the first n_check hypotheses for the oracle check."""
     evals = w.B * w.n_pairs * w.K
     out = {}
     for dtype in ("bf16", "f16"):
@@ -215,14 +221,33 @@ def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps):
         ws = sc.workspace(w.B, False)
         ms = timed(lambda: sc.cost(th_dev, w.K, w.R_mm, workspace=ws), steps, 2)
         out[dtype] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3), "roofline_frac_hbm": 16 * evals / (ms * 1e-3) / 8e12}
+        pairs_out[dtype] = sc.cost(th_dev[:n_check], w.K, w.R_mm, with_pairs=True)[1].cpu().numpy()
         sc.free()
     ws = scan32.workspace(w.B, False)
     ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, geom="f64", workspace=ws), steps, 2)
     out["f32_geom64"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3)}
+    pairs_out["f32_geom64"] = scan32.cost(th_dev[:n_check], w.K, w.R_mm, geom="f64", with_pairs=True)[1].cpu().numpy()
     wsg = scan32.workspace(w.B, True)
     ms = timed(lambda: scan32.cost_grad(th_dev, w.K, w.R_mm, workspace=wsg), max(3, steps // 2), 1)
     out["adjoint_f32"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
                           "note": "cost + gradient w.r.t. all B x N x 6 motion parameters"}
+    return out
+
+
+def oracle_check(w, ref, pairs_by_form):
+    """Every form's per-pair e against the FP64 oracle on the CPU baseline's
+    sample (its untimed pass computes them anyway): relative error per pair,
+    and the error of the sample's total."""
+    from oracle.ecc import pair_index
+
+    out = {"sample": f"{len(ref)} (hypothesis, pair) values: the CPU baseline's pairs x its hypotheses"}
+    keys = sorted(ref)
+    e_ref = np.array([ref[k] for k in keys])
+    for name, pairs in pairs_by_form.items():
+        got = np.array([pairs[h, pair_index(a, b, w.geom.n_views)] for h, a, b in keys], dtype=np.float64)
+        rel = np.abs(got - e_ref) / np.abs(e_ref)
+        out[name] = {"pair_rel_err_median": float(np.median(rel)), "pair_rel_err_max": float(rel.max()),
+                     "total_rel_err": float(abs(got.sum() - e_ref.sum()) / abs(e_ref.sum()))}
     return out
 
 
@@ -474,15 +499,19 @@ def main():
         "sino_build": {"ms": build_ms, "cells_per_s": cells / (build_ms * 1e-3),
                        "line_samples_per_s_upper": cells * n_s / (build_ms * 1e-3)},
     }
+    check_pairs = {args.dtype if args.geom == "f32" else f"{args.dtype}_geom64":
+                   scan.cost(th_dev[:8], w.K, w.R_mm, geom=args.geom, with_pairs=True)[1].cpu().numpy()}
     if not args.no_variants:
         _log("precision forms and adjoint")
-        rec["variants"] = measure_variants(eng, w, P, intr, imgs, scan, th_dev, max(3, args.steps // 2))
+        rec["variants"] = measure_variants(eng, w, P, intr, imgs, scan, th_dev, max(3, args.steps // 2),
+                                           check_pairs)
     if not args.no_variants and not args.no_pinv:
         _log("pseudo-inverse route vs the method")
         rec["pinv_ab"] = measure_pinv_ab(w, P, scan, thetas)
     if not args.no_cpu_baseline:
         _log("timing the FP64 oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(w, imgs, P, intr, thetas)
+        rec["oracle_check"] = oracle_check(w, rec["cpu_baseline"].pop("_oracle_e"), check_pairs)
     if not args.no_motion:
         del imgs
         torch.cuda.empty_cache()
