@@ -28,7 +28,12 @@ Readings (the paper is silent):
   into the symmetric pad row;
 * S = sign * (1 + t^2 / f^2) * interpolated value (Grangeat's weight on a flat
   detector, see ``sinogram.py``);
-* pairs a < b only, c = inf meaning e = d.
+* pairs a < b only, c = inf meaning e = d;
+* sampled arc of the pencil: the planes meeting the object sphere
+  (``pencil``), or, the other reading of which planes count, the connected
+  arc around kappa = 0 whose lines meet both detectors (kappa_range =
+  "detector", ``detector_kappa_arc``); K midpoint samples either way, and a
+  pair whose arc is empty contributes e = 0.
 """
 from __future__ import annotations
 
@@ -38,15 +43,22 @@ from dataclasses import dataclass
 import numpy as np
 
 from .dual import Dual, ops, value
-from .geometry import epipolar_line, epipolar_planes, moved_projection, pencil, plane_angles, source_position
+from .geometry import (detector_kappa_arc, epipolar_line, epipolar_planes, moved_projection, pencil,
+                       pencil_basis_lines, plane_angles, plane_angles_between, source_position)
 from .sinogram import SinoGrid
 
 
 @dataclass(frozen=True)
 class EccParams:
+    """K planes per pair; R_mm the object-sphere radius; c Eq. 16's Cauchy
+    parameter.  kappa_range picks the sampled arc of the pencil: "object",
+    the planes meeting the sphere of radius R_mm about the isocentre, or
+    "detector", the planes around kappa = 0 whose lines meet both detectors
+    (R_mm unused)."""
     K: int
     R_mm: float
     c: float = math.inf
+    kappa_range: str = "object"
 
 
 def pair_list(n_views: int):
@@ -108,14 +120,41 @@ def lookup(l, intr, grid: SinoGrid, sino, view):
     return S, hit
 
 
-def pair_geometry(P_a, P_b, theta_a, theta_b, params: EccParams):
-    """Moved projections, sources, sampled angles, planes and both lines."""
+def pair_kappa_arc(Pa, Pb, C_a, u1, u2, detector):
+    """The arc both detectors see: the intersection of each view's
+    ``detector_kappa_arc``; None when it is empty.  detector = (intr_a,
+    intr_b, W, H)."""
+    intr_a, intr_b, W, H = detector
+    arcs = []
+    for P, intr in ((Pa, intr_a), (Pb, intr_b)):
+        La, Lb = pencil_basis_lines(P, C_a, u1, u2, intr)
+        arc = detector_kappa_arc(La, Lb, W, H)
+        if arc is None:
+            return None
+        arcs.append(arc)
+    return max(arcs[0][0], arcs[1][0]), min(arcs[0][1], arcs[1][1])
+
+
+def pair_geometry(P_a, P_b, theta_a, theta_b, params: EccParams, detector=None):
+    """Moved projections, sources, sampled angles, planes and both lines.
+    With params.kappa_range == "detector" the angles sample the arc both
+    detectors see (``detector`` = (intr_a, intr_b, W, H) is then required);
+    kappa is None when that arc is empty."""
     Pa = moved_projection(P_a, theta_a)
     Pb = moved_projection(P_b, theta_b)
     C_a = source_position(Pa)
     C_b = source_position(Pb)
     u1, u2, kappa_max = pencil(C_a, C_b, params.R_mm)
-    kappa = plane_angles(kappa_max, params.K)
+    if params.kappa_range == "object":
+        kappa = plane_angles(kappa_max, params.K)
+    elif params.kappa_range == "detector":
+        arc = pair_kappa_arc(Pa, Pb, C_a, u1, u2, detector)
+        if arc is None:
+            return dict(Pa=Pa, Pb=Pb, C_a=C_a, C_b=C_b, u1=u1, u2=u2, kappa_max=kappa_max, kappa=None, E=None,
+                        l_a=None, l_b=None, arc=None)
+        kappa = plane_angles_between(arc[0], arc[1], params.K)
+    else:
+        raise ValueError(f"unknown kappa_range {params.kappa_range!r}")
     E = epipolar_planes(u1, u2, C_a, kappa)
     l_a, _ = epipolar_line(Pa, E)
     l_b, _ = epipolar_line(Pb, E)
@@ -141,7 +180,9 @@ def robust(d, c):
 
 def ecc_pair(P_a, P_b, theta_a, theta_b, intr_a, intr_b, grid: SinoGrid, sino, a, b, params: EccParams):
     """(e_ab, d_ab, N_kappa) for one view pair."""
-    g = pair_geometry(P_a, P_b, theta_a, theta_b, params)
+    g = pair_geometry(P_a, P_b, theta_a, theta_b, params, (intr_a, intr_b, grid.W, grid.H))
+    if g["kappa"] is None:
+        return robust(0.0, params.c), 0.0, 0
     S_a, hit_a = lookup(g["l_a"], intr_a, grid, sino, a)
     S_b, hit_b = lookup(g["l_b"], intr_b, grid, sino, b)
     d, N = inconsistency(S_a, S_b, hit_a & hit_b)
@@ -166,7 +207,11 @@ def ecc_cost(P, intr, theta, grid: SinoGrid, sino, params: EccParams, pairs=None
 
 
 def ecc_pair_grad(P_a, P_b, theta_a, theta_b, intr_a, intr_b, grid, sino, a, b, params: EccParams):
-    """e_ab and its exact derivative w.r.t. (theta_a, theta_b) (12 values)."""
+    """e_ab and its exact derivative w.r.t. (theta_a, theta_b) (12 values);
+    for the object-sphere range only (the detector arc's ends move with theta
+    and are not differentiated here)."""
+    if params.kappa_range != "object":
+        raise ValueError("the gradient is defined for kappa_range 'object' only")
     ta = [Dual.variable(theta_a[i], i, 12) for i in range(6)]
     tb = [Dual.variable(theta_b[i], 6 + i, 12) for i in range(6)]
     e, _, _ = ecc_pair(P_a, P_b, ta, tb, intr_a, intr_b, grid, sino, a, b, params)

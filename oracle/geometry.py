@@ -155,6 +155,76 @@ def plane_angles(kappa_max, K):
     return kappa_max * frac
 
 
+def plane_angles_between(lo, hi, K):
+    """Midpoint sampling of an arbitrary arc [lo, hi] with K planes,
+    kappa_k = lo + (k + 1/2) (hi - lo) / K."""
+    import numpy as np
+
+    return lo + (np.arange(K, dtype=np.float64) + 0.5) * ((hi - lo) / K)
+
+
+def pencil_basis_lines(P, C_a, u1, u2, intr):
+    """Image lines, offset about the principal point (l3 + l1 u0 + l2 v0), of
+    the pencil's two basis planes: normal u1 (kappa = 0) and normal u2
+    (kappa = pi/2), both through C_a.  Eqs. 13-14 are linear in the plane and
+    the plane at kappa is cos(kappa) E(u1) + sin(kappa) E(u2), so its line is
+    cos(kappa) La + sin(kappa) Lb."""
+    f, u0, v0 = (float(x) for x in intr)
+    out = []
+    for n in (u1, u2):
+        E = [n[0], n[1], n[2], -dot3(n, C_a)]
+        l, _ = epipolar_line(P, E)
+        out.append([l[0], l[1], l[2] + l[0] * u0 + l[1] * v0])
+    return out[0], out[1]
+
+
+def detector_kappa_arc(La, Lb, W, H):
+    """The arc of plane angles around kappa = 0 whose lines meet the closed
+    detector rectangle [-W/2, W/2] x [-H/2, H/2] (coordinates about the
+    principal point).  Returns (lo, hi) with lo <= 0 <= hi, None when the
+    plane at kappa = 0 misses the detector, and (-pi/2, pi/2) when every
+    plane meets it (the epipole lies on the detector).
+
+    A line meets the rectangle exactly when its value l . (x, y, 1) at the
+    four corners is not of one strict sign.  At corner c that value is
+    A_c cos(kappa) + B_c sin(kappa), which changes sign only at its zeros
+    kappa = atan2(-A_c, B_c) (mod pi); between consecutive zeros the
+    decision is constant.  The arc is found by stepping from 0 through the
+    sorted zeros in each direction until an interval misses.  Plain floats
+    (the values of Dual numbers are taken)."""
+    La = [float(_value(x)) for x in La]
+    Lb = [float(_value(x)) for x in Lb]
+    corners = [(sx * 0.5 * W, sy * 0.5 * H) for sx in (-1.0, 1.0) for sy in (-1.0, 1.0)]
+    AB = [(La[0] * x + La[1] * y + La[2], Lb[0] * x + Lb[1] * y + Lb[2]) for x, y in corners]
+
+    def meets(k):
+        c, s = math.cos(k), math.sin(k)
+        v = [A * c + B * s for A, B in AB]
+        return min(v) <= 0.0 <= max(v)
+
+    if not meets(0.0):
+        return None
+    zeros = []
+    for A, B in AB:
+        z = math.atan2(-A, B)
+        zeros.append((z + 0.5 * math.pi) % math.pi - 0.5 * math.pi)  # into [-pi/2, pi/2)
+    zeros.sort()
+
+    def walk(steps):
+        prev = 0.0
+        for k in steps:
+            if not meets(0.5 * (prev + k)):
+                return prev
+            prev = k
+        return None
+
+    hi = walk([z for z in zeros if z > 0.0] + [z + math.pi for z in zeros if z <= 0.0])
+    if hi is None:
+        return -0.5 * math.pi, 0.5 * math.pi
+    lo = walk([z for z in reversed(zeros) if z < 0.0] + [z - math.pi for z in reversed(zeros) if z >= 0.0])
+    return lo, hi
+
+
 def epipolar_planes(u1, u2, C_a, kappa):
     """E^kappa = (n, -n . C_a) for every sampled angle (homogeneous planes)."""
     c, s = ops.cos(kappa), ops.sin(kappa)
