@@ -184,6 +184,15 @@ def cpu_baseline(w, imgs_dev, P, intr, thetas, target_s=12.0, n_views=12, n_hyp=
                      f"evaluated {passes} times ({evals} evals in {dt:.1f} s; an untimed first pass "
                      f"filled the touched sinogram cells in {fill:.1f} s)"}
     out["_oracle_e"] = ref  # consumed by the oracle check, not printed
+    # the detector-bounded plane range on the first hypothesis (untimed)
+    t0 = time.perf_counter()
+    params_det = oracle.EccParams(w.K, w.R_mm, kappa_range="detector")
+    ref_det = {}
+    for a, b in pairs:
+        ref_det[(0, a, b)] = float(ecc_pair(as_rows(P[a]), as_rows(P[b]), list(thetas[0][a]), list(thetas[0][b]),
+                                            intr[a], intr[b], grid, lazy, a, b, params_det)[0])
+    _log(f"oracle: detector-range sample ({len(pairs)} pairs) in {time.perf_counter() - t0:.1f} s")
+    out["_oracle_e_detector"] = ref_det
     n_proc = min(16, os.cpu_count() or 1)
     if n_proc > 1:
         try:
@@ -227,6 +236,11 @@ def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps, pairs_out, n_
     ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, geom="f64", workspace=ws), steps, 2)
     out["f32_geom64"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3)}
     pairs_out["f32_geom64"] = scan32.cost(th_dev[:n_check], w.K, w.R_mm, geom="f64", with_pairs=True)[1].cpu().numpy()
+    ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, workspace=ws, kappa="detector"), steps, 2)
+    out["f32_detector_range"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
+                                 "note": "planes sample the arc both detectors see instead of the object sphere's"}
+    pairs_out["f32_detector_range"] = scan32.cost(th_dev[:1], w.K, w.R_mm, with_pairs=True,
+                                                  kappa="detector")[1].cpu().numpy()
     wsg = scan32.workspace(w.B, True)
     ms = timed(lambda: scan32.cost_grad(th_dev, w.K, w.R_mm, workspace=wsg), max(3, steps // 2), 1)
     out["adjoint_f32"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
@@ -234,18 +248,26 @@ def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps, pairs_out, n_
     return out
 
 
-def oracle_check(w, ref, pairs_by_form):
+def oracle_check(w, ref, pairs_by_form, ref_detector=None):
     """Every form's per-pair e against the FP64 oracle on the CPU baseline's
     sample (its untimed pass computes them anyway): relative error per pair,
-    and the error of the sample's total."""
+    and the error of the sample's total.  The detector-bounded range is
+    checked on the sample's first hypothesis (ref_detector)."""
     from oracle.ecc import pair_index
 
     out = {"sample": f"{len(ref)} (hypothesis, pair) values: the CPU baseline's pairs x its hypotheses"}
-    keys = sorted(ref)
-    e_ref = np.array([ref[k] for k in keys])
     for name, pairs in pairs_by_form.items():
+        r = ref
+        if name == "f32_detector_range":
+            if not ref_detector:
+                continue
+            r = ref_detector
+            out["sample_detector_range"] = f"{len(r)} pairs of the first hypothesis"
+        keys = sorted(r)
+        e_ref = np.array([r[k] for k in keys])
         got = np.array([pairs[h, pair_index(a, b, w.geom.n_views)] for h, a, b in keys], dtype=np.float64)
-        rel = np.abs(got - e_ref) / np.abs(e_ref)
+        zero = e_ref == 0.0  # a pair that sees no plane: exact 0 expected
+        rel = np.where(zero, np.where(got == 0.0, 0.0, np.inf), np.abs(got - e_ref) / np.where(zero, 1.0, np.abs(e_ref)))
         out[name] = {"pair_rel_err_median": float(np.median(rel)), "pair_rel_err_max": float(rel.max()),
                      "total_rel_err": float(abs(got.sum() - e_ref.sum()) / abs(e_ref.sum()))}
     return out
@@ -511,7 +533,8 @@ def main():
     if not args.no_cpu_baseline:
         _log("timing the FP64 oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(w, imgs, P, intr, thetas)
-        rec["oracle_check"] = oracle_check(w, rec["cpu_baseline"].pop("_oracle_e"), check_pairs)
+        rec["oracle_check"] = oracle_check(w, rec["cpu_baseline"].pop("_oracle_e"), check_pairs,
+                                           rec["cpu_baseline"].pop("_oracle_e_detector", None))
     if not args.no_motion:
         del imgs
         torch.cuda.empty_cache()

@@ -54,6 +54,8 @@ enum { ECC_F32 = 0, ECC_BF16 = 1, ECC_F16 = 2 };
  * The per-view and per-pair geometry (moved projection, sources, baseline,
  * pencil of planes) is always FP64. */
 enum { ECC_GEOM_F32 = 0, ECC_GEOM_F64 = 1 };
+/* Which arc of the pencil of epipolar planes an evaluation samples. */
+enum { ECC_KAPPA_OBJECT = 0, ECC_KAPPA_DETECTOR = 1 };
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *ecc_last_error(void);
@@ -115,17 +117,31 @@ ecc_status ecc_scan_bytes(ecc_ctx *ctx, int32_t scan_id, uint64_t *bytes);
 
 /* Evaluation parameters.
  *   K     number of epipolar planes sampled per pair (Eq. 15), 1..4096;
- *   R_mm  radius of the isocentric object sphere: the pencil of planes about
- *         the baseline C_a C_b is sampled over the angles whose planes meet
- *         that sphere, kappa_k = -kappa_max + (k + 1/2) 2 kappa_max / K with
- *         kappa_max = asin(min(1, R_mm / h)), h = baseline-isocentre distance;
+ *   R_mm  radius of the isocentric object sphere (positive, finite; used by
+ *         ECC_KAPPA_OBJECT only);
  *   c     Cauchy parameter of Eq. 16 (c <= 0 or infinite means e = d);
- *   geom  ECC_GEOM_F32 or ECC_GEOM_F64 (per-plane geometry precision). */
+ *   geom  ECC_GEOM_F32 or ECC_GEOM_F64 (per-plane geometry precision);
+ *   kappa_range  which planes of the pencil about the baseline C_a C_b are
+ *         sampled (the paper leaves the range open, Sec. "Epipolar
+ *         Consistency" and Eq. 15's N):
+ *     ECC_KAPPA_OBJECT    the planes that meet the object sphere,
+ *                         kappa_k = -kappa_max + (k + 1/2) 2 kappa_max / K,
+ *                         kappa_max = asin(min(1, R_mm / h)), h = distance
+ *                         of the baseline from the isocentre;
+ *     ECC_KAPPA_DETECTOR  the arc around kappa = 0 (the plane through the
+ *                         isocentre) whose lines meet both detectors,
+ *                         kappa_k = lo + (k + 1/2) (hi - lo) / K; a pair
+ *                         whose plane at kappa = 0 misses a detector has
+ *                         e = 0.  Cost only: ecc_cost_grad refuses it
+ *                         (the arc's ends move with theta);
+ *   reserved  must be 0. */
 typedef struct {
     int32_t K;
     int32_t geom;
     double R_mm;
     double c;
+    int32_t kappa_range;
+    int32_t reserved;
 } ecc_eval_params;
 
 /* Device workspace (bytes) an evaluation of B hypotheses needs; with_grad

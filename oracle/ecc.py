@@ -121,10 +121,14 @@ def lookup(l, intr, grid: SinoGrid, sino, view):
 
 
 def pair_kappa_arc(Pa, Pb, C_a, u1, u2, detector):
-    """The arc both detectors see: the intersection of each view's
-    ``detector_kappa_arc``; None when it is empty.  detector = (intr_a,
-    intr_b, W, H)."""
+    """The arc both detectors see: the part around kappa = 0 of the
+    intersection of the two views' ``detector_kappa_arc``; None when it is
+    empty.  A view that sees every plane leaves the other view's arc as it
+    is (that arc may reach past +-pi/2); two partial arcs, each shorter than
+    pi and containing 0, meet around 0 in [max of the lows, min of the
+    highs].  detector = (intr_a, intr_b, W, H)."""
     intr_a, intr_b, W, H = detector
+    full = (-0.5 * math.pi, 0.5 * math.pi)
     arcs = []
     for P, intr in ((Pa, intr_a), (Pb, intr_b)):
         La, Lb = pencil_basis_lines(P, C_a, u1, u2, intr)
@@ -132,6 +136,10 @@ def pair_kappa_arc(Pa, Pb, C_a, u1, u2, detector):
         if arc is None:
             return None
         arcs.append(arc)
+    if arcs[0] == full:
+        return arcs[1]
+    if arcs[1] == full:
+        return arcs[0]
     return max(arcs[0][0], arcs[1][0]), min(arcs[0][1], arcs[1][1])
 
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libecc.so")
 ECC_OK, ECC_E_ARG, ECC_E_BUDGET, ECC_E_HIP, ECC_E_STATE, ECC_E_NOSCAN = 0, -1, -2, -3, -4, -5
 ECC_F32, ECC_BF16, ECC_F16 = 0, 1, 2
 ECC_GEOM_F32, ECC_GEOM_F64 = 0, 1
+ECC_KAPPA_OBJECT, ECC_KAPPA_DETECTOR = 0, 1
 DTYPES = {"f32": ECC_F32, "bf16": ECC_BF16, "f16": ECC_F16}
 
 # every symbol include/ecc.h declares
@@ -36,7 +37,8 @@ class EccError(RuntimeError):
 
 
 class EvalParams(ctypes.Structure):
-    _fields_ = [("K", ctypes.c_int32), ("geom", ctypes.c_int32), ("R_mm", ctypes.c_double), ("c", ctypes.c_double)]
+    _fields_ = [("K", ctypes.c_int32), ("geom", ctypes.c_int32), ("R_mm", ctypes.c_double), ("c", ctypes.c_double),
+                ("kappa_range", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RequestStats(ctypes.Structure):

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(const float *__restrict
     pair_from_index(p, ec.n_views, a, b);
     PairConst<G> pc;
     const int64_t ga = (int64_t)hyp * ec.n_views + a, gb = (int64_t)hyp * ec.n_views + b;
-    pair_setup<G>(vt[ga], vt[gb], ec.R_mm, ec.K, pc, pinv ? pinv + 12 * ga : nullptr,
+    pair_setup<G>(vt[ga], vt[gb], ec, pc, pinv ? pinv + 12 * ga : nullptr,
                   pinv ? pinv + 12 * gb : nullptr);
     pc.va = a;
     pc.vb = b;

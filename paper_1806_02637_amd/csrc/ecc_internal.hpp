@@ -65,6 +65,7 @@ struct EvalConsts {
     float half_w, half_h;
     // t0 = t_max + dt: (t + t0) / dt is the stored column coordinate of t
     float t0, inv_dt, inv_dalpha;
+    int32_t kappa_detector;  // 1: planes sample the arc both detectors see (else the object sphere's)
     double t0_d, inv_dt_d, inv_dalpha_d;
 };
 

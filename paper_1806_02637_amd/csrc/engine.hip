@@ -162,6 +162,9 @@ ecc_status check_eval(ecc_ctx *ctx, int32_t scan_id, int32_t B, const ecc_eval_p
     if (!(prm->R_mm > 0.0) || !isfinite(prm->R_mm)) return fail(ECC_E_ARG, "R_mm must be positive and finite");
     if (prm->geom != ECC_GEOM_F32 && prm->geom != ECC_GEOM_F64) return fail(ECC_E_ARG, "unknown geom %d", prm->geom);
     if (isnan(prm->c)) return fail(ECC_E_ARG, "c is NaN");
+    if (prm->kappa_range != ECC_KAPPA_OBJECT && prm->kappa_range != ECC_KAPPA_DETECTOR)
+        return fail(ECC_E_ARG, "unknown kappa_range %d", prm->kappa_range);
+    if (prm->reserved != 0) return fail(ECC_E_ARG, "reserved field must be 0");
     *out = s;
     return ECC_OK;
 }
@@ -178,6 +181,7 @@ EvalConsts make_consts(const Scan *s, int B, const ecc_eval_params *prm) {
     ec.view_elems = s->layout.view_elems;
     ec.geom64 = prm->geom == ECC_GEOM_F64;
     ec.R_mm = prm->R_mm;
+    ec.kappa_detector = prm->kappa_range == ECC_KAPPA_DETECTOR;
     ec.inv_c = (prm->c > 0.0 && isfinite(prm->c)) ? (float)(1.0 / prm->c) : 0.0f;
     ec.half_w = 0.5f * s->W;
     ec.half_h = 0.5f * s->H;
@@ -551,6 +555,8 @@ ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double 
     Scan *s = nullptr;
     ecc_status st;
     if ((st = check_eval(ctx, scan_id, B, params, &s))) return st;
+    if (params->kappa_range != ECC_KAPPA_OBJECT)
+        return fail(ECC_E_ARG, "the gradient is defined for kappa_range ECC_KAPPA_OBJECT only");
     if (!theta_dev || !out_cost_dev || !grad_dev || !workspace_dev) return fail(ECC_E_ARG, "null device pointer");
     const Workspace w = workspace_layout(s, B, true);
     if (workspace_bytes < w.total)

@@ -107,9 +107,14 @@ class Scan:
         return ws
 
     @staticmethod
-    def params(K: int, R_mm: float, c: float = math.inf, geom: str = "f32") -> B.EvalParams:
+    def params(K: int, R_mm: float, c: float = math.inf, geom: str = "f32", kappa: str = "object") -> B.EvalParams:
+        """kappa: "object" (planes meeting the object sphere of radius R_mm)
+        or "detector" (the arc around kappa = 0 both detectors see)."""
+        if kappa not in ("object", "detector"):
+            raise ValueError(f"kappa must be 'object' or 'detector', got {kappa!r}")
         return B.EvalParams(int(K), B.ECC_GEOM_F64 if geom == "f64" else B.ECC_GEOM_F32, float(R_mm),
-                            0.0 if math.isinf(c) else float(c))
+                            0.0 if math.isinf(c) else float(c),
+                            B.ECC_KAPPA_DETECTOR if kappa == "detector" else B.ECC_KAPPA_OBJECT, 0)
 
     def _theta(self, theta) -> torch.Tensor:
         th = torch.as_tensor(theta, dtype=torch.float64)
@@ -120,14 +125,14 @@ class Scan:
         return th.to(self.engine.device).contiguous()
 
     def cost(self, theta, K: int, R_mm: float, c: float = math.inf, geom: str = "f32", with_pairs: bool = False,
-             workspace: torch.Tensor | None = None):
+             workspace: torch.Tensor | None = None, kappa: str = "object"):
         """Returns cost [B] (FP64 device tensor) and, with_pairs, e [B, n_pairs]."""
         th = self._theta(theta)
         Bn = th.shape[0]
         out = torch.empty(Bn, dtype=torch.float64, device=self.engine.device)
         pairs = torch.empty((Bn, self.n_pairs), dtype=torch.float32, device=self.engine.device) if with_pairs else None
         ws = self.workspace(Bn, False) if workspace is None else workspace
-        B.ecc_cost(self.ctx, self.id, Bn, th.data_ptr(), self.params(K, R_mm, c, geom), out.data_ptr(),
+        B.ecc_cost(self.ctx, self.id, Bn, th.data_ptr(), self.params(K, R_mm, c, geom, kappa), out.data_ptr(),
                    pairs.data_ptr() if pairs is not None else 0, ws.data_ptr(), ws.numel(),
                    _stream_handle(self.engine.device))
         return (out, pairs) if with_pairs else out

@@ -65,7 +65,8 @@ class PinvRoute:
         self.host_ms = []  # host pseudo-inverse time per call
         self._copied = None  # event after the last upload from the staging buffer
 
-    def cost(self, theta_host: np.ndarray, K: int, R_mm: float, c: float = math.inf, with_pairs: bool = False):
+    def cost(self, theta_host: np.ndarray, K: int, R_mm: float, c: float = math.inf, with_pairs: bool = False,
+             kappa: str = "object"):
         th = np.asarray(theta_host, dtype=np.float64)
         if th.ndim == 2:
             th = th[None]
@@ -84,6 +85,6 @@ class PinvRoute:
         pairs = torch.empty((Bn, self.scan.n_pairs), dtype=torch.float32, device=dev) if with_pairs else None
         ws = self.scan.workspace(Bn, False)
         B.ecc_cost_pinv(self.scan.ctx, self.scan.id, Bn, th_dev.data_ptr(), self.dev.data_ptr(),
-                        self.scan.params(K, R_mm, c), out.data_ptr(), pairs.data_ptr() if pairs is not None else 0,
+                        self.scan.params(K, R_mm, c, kappa=kappa), out.data_ptr(), pairs.data_ptr() if pairs is not None else 0,
                         ws.data_ptr(), ws.numel(), _stream_handle(dev))
         return (out, pairs) if with_pairs else out

@@ -3,6 +3,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -32,8 +33,23 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def test_status_codes_and_eval_params_layout():
-    assert ctypes.sizeof(binding.EvalParams) == 24
+def test_status_codes_and_eval_params_layout(tmp_path):
+    # the ctypes mirror must match the C header's struct, field by field
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "ecc.h"\n'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ecc_eval_params),'
+        ' offsetof(ecc_eval_params, K), offsetof(ecc_eval_params, geom), offsetof(ecc_eval_params, R_mm),'
+        ' offsetof(ecc_eval_params, c), offsetof(ecc_eval_params, kappa_range),'
+        ' offsetof(ecc_eval_params, reserved)); return 0; }\n')
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    c_layout = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    E = binding.EvalParams
+    py_layout = [ctypes.sizeof(E)] + [getattr(E, f).offset for f in ("K", "geom", "R_mm", "c", "kappa_range", "reserved")]
+    assert c_layout == py_layout
+    assert (binding.ECC_KAPPA_OBJECT, binding.ECC_KAPPA_DETECTOR) == (0, 1)
     assert (binding.ECC_OK, binding.ECC_E_ARG, binding.ECC_E_BUDGET, binding.ECC_E_HIP, binding.ECC_E_STATE,
             binding.ECC_E_NOSCAN) == (0, -1, -2, -3, -4, -5)
 

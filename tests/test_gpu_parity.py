@@ -130,7 +130,7 @@ def test_repeated_calls_are_bitwise_identical(eng, small):
     scan.free()
 
 
-def _sampled_workload_check(eng, name, B, n_cells, n_pairs_check, seed):
+def _sampled_workload_check(eng, name, B, n_cells, n_pairs_check, seed, kappa="object"):
     """Full-size workload in the configuration the benchmark times: all B
     hypotheses evaluated on the GPU; sampled sinogram cells and sampled
     (hypothesis, pair) values recomputed one by one by the oracle from the
@@ -144,7 +144,7 @@ def _sampled_workload_check(eng, name, B, n_cells, n_pairs_check, seed):
     scan = eng.load_scan(P, intr, imgs)
     scan.build_sinograms(w.n_alpha, w.n_t, w.ds_px, "f32")
     thetas = w.motion(B)
-    cost, pairs = scan.cost(thetas, w.K, w.R_mm, with_pairs=True)
+    cost, pairs = scan.cost(thetas, w.K, w.R_mm, with_pairs=True, kappa=kappa)
     cost, pairs = cost.cpu().numpy(), pairs.cpu().numpy()
     rng = np.random.default_rng(seed)
     pair_ids = np.sort(rng.choice(w.n_pairs, n_pairs_check, replace=False))
@@ -178,7 +178,7 @@ def _sampled_workload_check(eng, name, B, n_cells, n_pairs_check, seed):
         scale = np.abs(scan.read_sinogram(v)).max()
         assert np.abs(got - ref).max() <= 2e-5 * scale, (v, np.abs(got - ref).max() / scale)
     # sampled pairs, every hypothesis for the first pairs, two for the rest
-    params = oracle.EccParams(w.K, w.R_mm)
+    params = oracle.EccParams(w.K, w.R_mm, kappa_range=kappa)
     worst = 0.0
     for i, ((a, b), pid) in enumerate(zip(sel, pair_ids)):
         hyps = range(B) if i < 2 else (0, B - 1)
@@ -189,7 +189,7 @@ def _sampled_workload_check(eng, name, B, n_cells, n_pairs_check, seed):
             err = abs(pairs[h, pid] - e_ref)
             worst = max(worst, err / max(abs(e_ref), 1e-30))
             assert err <= 2e-4 * abs(e_ref) + 1e-7, (name, h, a, b, pairs[h, pid], e_ref)
-    _say(f"{name}: worst sampled pair rel err {worst:.2e}")
+    _say(f"{name} ({kappa} range): worst sampled pair rel err {worst:.2e}")
     # the total is the fixed-order sum of the per-pair values
     assert np.allclose(cost, pairs.astype(np.float64).sum(1), rtol=1e-6)
     scan.free()
@@ -203,3 +203,8 @@ def test_mid248_sampled_parity(eng):
 def test_full496_sampled_parity(eng):
     _say("case: full496 sampled parity, B=32, K=512")
     _sampled_workload_check(eng, "full496", 32, 200, 8, 12)
+
+
+def test_full496_detector_range_sampled_parity(eng):
+    _say("case: full496 sampled parity, detector-bounded plane range, B=32, K=512")
+    _sampled_workload_check(eng, "full496", 32, 50, 4, 13, kappa="detector")

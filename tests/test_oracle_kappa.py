@@ -72,6 +72,11 @@ def _pairs_under_test():
             th_a = np.concatenate([rng.normal(0, 3, 3), rng.normal(0, 40, 3)])
             th_b = np.concatenate([rng.normal(0, 3, 3), rng.normal(0, 40, 3)])
             cases.append((g, P, intr, R, a, b, th_a, th_b))
+    # one view sees every plane, the other's arc reaches past +-pi/2
+    cases.append((g, P, intr, R, 0, 10, np.array([-3.717, -4.609, -2.289, 13.212, -60.577, -12.551]),
+                  np.array([-0.796, 2.704, 1.073, 21.322, -39.23, -7.777])))
+    cases.append((g, P, intr, R, 0, 10, np.array([-3.773, 8.446, -1.437, 94.464, -25.967, -44.129]),
+                  np.array([1.249, 5.157, 0.805, -35.132, -80.473, -84.091])))
     # a view shifted 900 mm along the rotation axis: the isocentre leaves its detector
     cases.append((g, P, intr, R, 0, 4, zero, np.array([0, 0, 0, 0.0, 0.0, 900.0])))
     return cases
@@ -80,7 +85,7 @@ def _pairs_under_test():
 def test_arc_matches_brute_force_scan():
     grid = (np.arange(N_SCAN) + 0.5) * (math.pi / N_SCAN) - 0.5 * math.pi
     step = math.pi / N_SCAN
-    seen = {"full": 0, "arc": 0, "none": 0}
+    seen = {"full": 0, "arc": 0, "none": 0, "wide": 0}
     for g, P, intr, R, a, b, th_a, th_b in _pairs_under_test():
         Pa, Pb, C_a, C_b, u1, u2, km = _setup(P[a], P[b], th_a, th_b, R)
         for Pv, iv in ((Pa, intr[a]), (Pb, intr[b])):
@@ -107,7 +112,8 @@ def test_arc_matches_brute_force_scan():
             assert pa == (-0.5 * math.pi, 0.5 * math.pi)
         else:
             assert abs(pa[0] - bp[0]) <= step + 1e-12 and abs(pa[1] - bp[1]) <= step + 1e-12
-    assert seen["full"] > 0 and seen["arc"] > 0 and seen["none"] > 0, seen
+            seen["wide"] += pa[0] < -0.5 * math.pi or pa[1] > 0.5 * math.pi
+    assert min(seen.values()) > 0, seen
 
 
 def _epipole_on_detector(P, C_other, intr, W, H):
