@@ -218,10 +218,11 @@ def timed(fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps, pairs_out, n_check=8):
+def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps, pairs_out, n_check=8, detector_range=True):
     """Precision forms and the adjoint on the same workload, each against the
     plain FP32 step (same GPU, same inputs).  pairs_out[name] receives the
-    per-pair e of the first n_check hypotheses for the oracle check."""
+    per-pair e of the first n_check hypotheses for the oracle check (None:
+    no check, no extra launches)."""
     evals = w.B * w.n_pairs * w.K
     out = {}
     for dtype in ("bf16", "f16"):
@@ -230,17 +231,22 @@ def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps, pairs_out, n_
         ws = sc.workspace(w.B, False)
         ms = timed(lambda: sc.cost(th_dev, w.K, w.R_mm, workspace=ws), steps, 2)
         out[dtype] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3), "roofline_frac_hbm": 16 * evals / (ms * 1e-3) / 8e12}
-        pairs_out[dtype] = sc.cost(th_dev[:n_check], w.K, w.R_mm, with_pairs=True)[1].cpu().numpy()
+        if pairs_out is not None:
+            pairs_out[dtype] = sc.cost(th_dev[:n_check], w.K, w.R_mm, with_pairs=True)[1].cpu().numpy()
         sc.free()
     ws = scan32.workspace(w.B, False)
     ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, geom="f64", workspace=ws), steps, 2)
     out["f32_geom64"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3)}
-    pairs_out["f32_geom64"] = scan32.cost(th_dev[:n_check], w.K, w.R_mm, geom="f64", with_pairs=True)[1].cpu().numpy()
-    ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, workspace=ws, kappa="detector"), steps, 2)
-    out["f32_detector_range"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
-                                 "note": "planes sample the arc both detectors see instead of the object sphere's"}
-    pairs_out["f32_detector_range"] = scan32.cost(th_dev[:1], w.K, w.R_mm, with_pairs=True,
-                                                  kappa="detector")[1].cpu().numpy()
+    if pairs_out is not None:
+        pairs_out["f32_geom64"] = scan32.cost(th_dev[:n_check], w.K, w.R_mm, geom="f64",
+                                              with_pairs=True)[1].cpu().numpy()
+    if detector_range:
+        ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, workspace=ws, kappa="detector"), steps, 2)
+        out["f32_detector_range"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
+                                     "note": "planes sample the arc both detectors see instead of the object sphere's"}
+        if pairs_out is not None:
+            pairs_out["f32_detector_range"] = scan32.cost(th_dev[:1], w.K, w.R_mm, with_pairs=True,
+                                                          kappa="detector")[1].cpu().numpy()
     wsg = scan32.workspace(w.B, True)
     ms = timed(lambda: scan32.cost_grad(th_dev, w.K, w.R_mm, workspace=wsg), max(3, steps // 2), 1)
     out["adjoint_f32"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
@@ -421,6 +427,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-motion", action="store_true")
     ap.add_argument("--no-pinv", action="store_true")
+    ap.add_argument("--no-detector-range", action="store_true",
+                    help="skip the detector-bounded plane range variant (it launches the same forward kernel)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ecc_fwd_full496_traffic.json"))
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -521,12 +529,17 @@ def main():
         "sino_build": {"ms": build_ms, "cells_per_s": cells / (build_ms * 1e-3),
                        "line_samples_per_s_upper": cells * n_s / (build_ms * 1e-3)},
     }
-    check_pairs = {args.dtype if args.geom == "f32" else f"{args.dtype}_geom64":
-                   scan.cost(th_dev[:8], w.K, w.R_mm, geom=args.geom, with_pairs=True)[1].cpu().numpy()}
+    # per-pair values for the oracle check; only with the CPU baseline, whose
+    # pass supplies the oracle's values (extra launches would also mix into
+    # profiler averages of the timed kernel)
+    check_pairs = None
+    if not args.no_cpu_baseline:
+        check_pairs = {args.dtype if args.geom == "f32" else f"{args.dtype}_geom64":
+                       scan.cost(th_dev[:8], w.K, w.R_mm, geom=args.geom, with_pairs=True)[1].cpu().numpy()}
     if not args.no_variants:
         _log("precision forms and adjoint")
         rec["variants"] = measure_variants(eng, w, P, intr, imgs, scan, th_dev, max(3, args.steps // 2),
-                                           check_pairs)
+                                           check_pairs, detector_range=not args.no_detector_range)
     if not args.no_variants and not args.no_pinv:
         _log("pseudo-inverse route vs the method")
         rec["pinv_ab"] = measure_pinv_ab(w, P, scan, thetas)

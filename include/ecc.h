@@ -132,8 +132,9 @@ ecc_status ecc_scan_bytes(ecc_ctx *ctx, int32_t scan_id, uint64_t *bytes);
  *                         isocentre) whose lines meet both detectors,
  *                         kappa_k = lo + (k + 1/2) (hi - lo) / K; a pair
  *                         whose plane at kappa = 0 misses a detector has
- *                         e = 0.  Cost only: ecc_cost_grad refuses it
- *                         (the arc's ends move with theta);
+ *                         e = 0.  The arc's ends move with theta: the
+ *                         gradient follows each end as the zero angle of
+ *                         the detector corner whose line fixes it;
  *   reserved  must be 0. */
 typedef struct {
     int32_t K;

@@ -43,7 +43,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .dual import Dual, ops, value
-from .geometry import (detector_kappa_arc, epipolar_line, epipolar_planes, moved_projection, pencil,
+from .geometry import (arc_end, detector_kappa_arc, epipolar_line, epipolar_planes, moved_projection, pencil,
                        pencil_basis_lines, plane_angles, plane_angles_between, source_position)
 from .sinogram import SinoGrid
 
@@ -120,27 +120,49 @@ def lookup(l, intr, grid: SinoGrid, sino, view):
     return S, hit
 
 
+ARC_TIE = 1e-9  # rad: two views' arc ends this close are one kink
+
+
 def pair_kappa_arc(Pa, Pb, C_a, u1, u2, detector):
     """The arc both detectors see: the part around kappa = 0 of the
     intersection of the two views' ``detector_kappa_arc``; None when it is
     empty.  A view that sees every plane leaves the other view's arc as it
     is (that arc may reach past +-pi/2); two partial arcs, each shorter than
     pi and containing 0, meet around 0 in [max of the lows, min of the
-    highs].  detector = (intr_a, intr_b, W, H)."""
+    highs].  detector = (intr_a, intr_b, W, H).
+
+    With Dual geometry the ends are Dual: each is the zero angle of the
+    corner that fixes it.  Where the two views' ends agree within ARC_TIE
+    (a circular orbit without motion makes them equal) the end is a kink
+    between two smooth branches; its derivative is taken as their mean, the
+    value central differences give there."""
     intr_a, intr_b, W, H = detector
     full = (-0.5 * math.pi, 0.5 * math.pi)
     arcs = []
     for P, intr in ((Pa, intr_a), (Pb, intr_b)):
         La, Lb = pencil_basis_lines(P, C_a, u1, u2, intr)
-        arc = detector_kappa_arc(La, Lb, W, H)
+        arc = detector_kappa_arc(La, Lb, W, H, ends=True)
         if arc is None:
             return None
-        arcs.append(arc)
-    if arcs[0] == full:
-        return arcs[1]
-    if arcs[1] == full:
-        return arcs[0]
-    return max(arcs[0][0], arcs[1][0]), min(arcs[0][1], arcs[1][1])
+        arcs.append((arc, La, Lb))
+    (a, La_a, Lb_a), (b, La_b, Lb_b) = arcs
+    dual = isinstance(La_a[0], Dual)
+
+    def end(i, view):  # end i (0 low, 1 high) of one view's arc
+        arc, La, Lb = arcs[view]
+        src = arc[2 + i]
+        return arc[i] if (src is None or not dual) else arc_end(La, Lb, W, H, src)
+
+    def pick(i, better):
+        if a[:2] == full:
+            return end(i, 1)
+        if b[:2] == full:
+            return end(i, 0)
+        if abs(a[i] - b[i]) <= ARC_TIE:
+            return 0.5 * (end(i, 0) + end(i, 1)) if dual else better(a[i], b[i])
+        return end(i, 0) if better(a[i], b[i]) == a[i] else end(i, 1)
+
+    return pick(0, max), pick(1, min)
 
 
 def pair_geometry(P_a, P_b, theta_a, theta_b, params: EccParams, detector=None):
@@ -215,11 +237,10 @@ def ecc_cost(P, intr, theta, grid: SinoGrid, sino, params: EccParams, pairs=None
 
 
 def ecc_pair_grad(P_a, P_b, theta_a, theta_b, intr_a, intr_b, grid, sino, a, b, params: EccParams):
-    """e_ab and its exact derivative w.r.t. (theta_a, theta_b) (12 values);
-    for the object-sphere range only (the detector arc's ends move with theta
-    and are not differentiated here)."""
-    if params.kappa_range != "object":
-        raise ValueError("the gradient is defined for kappa_range 'object' only")
+    """e_ab and its exact derivative w.r.t. (theta_a, theta_b) (12 values).
+    With the detector-bounded range the arc's ends move with theta through
+    the zero angles of the corners that fix them; that motion is part of the
+    derivative (the choice of corner is held, as the choice of cell is)."""
     ta = [Dual.variable(theta_a[i], i, 12) for i in range(6)]
     tb = [Dual.variable(theta_b[i], 6 + i, 12) for i in range(6)]
     e, _, _ = ecc_pair(P_a, P_b, ta, tb, intr_a, intr_b, grid, sino, a, b, params)

@@ -160,7 +160,8 @@ def plane_angles_between(lo, hi, K):
     kappa_k = lo + (k + 1/2) (hi - lo) / K."""
     import numpy as np
 
-    return lo + (np.arange(K, dtype=np.float64) + 0.5) * ((hi - lo) / K)
+    frac = (np.arange(K, dtype=np.float64) + 0.5) / K
+    return lo + ((hi - lo) * frac)
 
 
 def pencil_basis_lines(P, C_a, u1, u2, intr):
@@ -178,7 +179,7 @@ def pencil_basis_lines(P, C_a, u1, u2, intr):
     return out[0], out[1]
 
 
-def detector_kappa_arc(La, Lb, W, H):
+def detector_kappa_arc(La, Lb, W, H, ends=False):
     """The arc of plane angles around kappa = 0 whose lines meet the closed
     detector rectangle [-W/2, W/2] x [-H/2, H/2] (coordinates about the
     principal point).  Returns (lo, hi) with lo <= 0 <= hi, None when the
@@ -191,10 +192,15 @@ def detector_kappa_arc(La, Lb, W, H):
     kappa = atan2(-A_c, B_c) (mod pi); between consecutive zeros the
     decision is constant.  The arc is found by stepping from 0 through the
     sorted zeros in each direction until an interval misses.  Plain floats
-    (the values of Dual numbers are taken)."""
+    (the values of Dual numbers are taken).
+
+    With ends=True, also returns for each end the (corner, m) for which the
+    end equals atan2(-A_c, B_c) + m pi (None for the fixed ends of a whole
+    half circle), so that a caller can follow the ends' dependence on the
+    lines."""
     La = [float(_value(x)) for x in La]
     Lb = [float(_value(x)) for x in Lb]
-    corners = [(sx * 0.5 * W, sy * 0.5 * H) for sx in (-1.0, 1.0) for sy in (-1.0, 1.0)]
+    corners = detector_corners(W, H)
     AB = [(La[0] * x + La[1] * y + La[2], Lb[0] * x + Lb[1] * y + Lb[2]) for x, y in corners]
 
     def meets(k):
@@ -204,25 +210,46 @@ def detector_kappa_arc(La, Lb, W, H):
 
     if not meets(0.0):
         return None
-    zeros = []
-    for A, B in AB:
-        z = math.atan2(-A, B)
-        zeros.append((z + 0.5 * math.pi) % math.pi - 0.5 * math.pi)  # into [-pi/2, pi/2)
-    zeros.sort()
+    raw = [math.atan2(-A, B) for A, B in AB]
+    # zero of each corner, into [-pi/2, pi/2), with its corner
+    zeros = sorted(((r + 0.5 * math.pi) % math.pi - 0.5 * math.pi, c) for c, r in enumerate(raw))
 
     def walk(steps):
-        prev = 0.0
-        for k in steps:
+        prev, src = 0.0, None
+        for k, c in steps:
             if not meets(0.5 * (prev + k)):
-                return prev
-            prev = k
+                return prev, src
+            prev, src = k, c
         return None
 
-    hi = walk([z for z in zeros if z > 0.0] + [z + math.pi for z in zeros if z <= 0.0])
-    if hi is None:
-        return -0.5 * math.pi, 0.5 * math.pi
-    lo = walk([z for z in reversed(zeros) if z < 0.0] + [z - math.pi for z in reversed(zeros) if z >= 0.0])
-    return lo, hi
+    up = walk([(z, c) for z, c in zeros if z > 0.0] + [(z + math.pi, c) for z, c in zeros if z <= 0.0])
+    if up is None:
+        return (-0.5 * math.pi, 0.5 * math.pi, None, None) if ends else (-0.5 * math.pi, 0.5 * math.pi)
+    down = walk([(z, c) for z, c in reversed(zeros) if z < 0.0] +
+                [(z - math.pi, c) for z, c in reversed(zeros) if z >= 0.0])
+    (hi, c_hi), (lo, c_lo) = up, down
+    if not ends:
+        return lo, hi
+
+    def end(k, c):
+        return None if c is None else (c, round((k - raw[c]) / math.pi))
+
+    return lo, hi, end(lo, c_lo), end(hi, c_hi)
+
+
+def detector_corners(W, H):
+    """The four corners of the detector rectangle about the principal point."""
+    return [(sx * 0.5 * W, sy * 0.5 * H) for sx in (-1.0, 1.0) for sy in (-1.0, 1.0)]
+
+
+def arc_end(La, Lb, W, H, end):
+    """An arc end given as (corner, m) by ``detector_kappa_arc``, as
+    atan2(-A_c, B_c) + m pi of the lines La, Lb (generic over Dual)."""
+    c, m = end
+    x, y = detector_corners(W, H)[c]
+    A = La[0] * x + La[1] * y + La[2]
+    B = Lb[0] * x + Lb[1] * y + Lb[2]
+    return ops.arctan2(-A, B) + m * math.pi
 
 
 def epipolar_planes(u1, u2, C_a, kappa):

@@ -9,11 +9,17 @@
 //                    detectors; through the weighted bilinear lookup to
 //                    (alpha, t), through atan2 / offset to the line l, through
 //                    l = H (cos k, sin k) to the 6 + 6 line-map entries and to
-//                    kappa_max (k = kappa_max ((2k+1)/K - 1)); fixed-order wave
-//                    sums of those 13 sensitivities, written per pair.
+//                    the sampled arc: kappa_max for the object-sphere range
+//                    (k = kappa_max ((2k+1)/K - 1)), or its two ends lo, hi for
+//                    the detector-bounded range (k = lo + (k+1/2)(hi - lo)/K);
+//                    fixed-order wave sums of those 14 sensitivities, written
+//                    per pair.
 // pair_tangent  one thread per (hypothesis, pair, motion parameter): an FP64
 //               forward-mode (dual number) sweep of the pair's geometry seeded
-//               with dP'/dtheta, contracted with the 13 sensitivities.
+//               with dP'/dtheta, contracted with the 14 sensitivities.  A
+//               detector arc's end moves as the zero angle of the corner that
+//               fixes it, atan2(-A_c, B_c) with (A_c, B_c) the two basis
+//               lines' values at the corner.
 // reduce_grad   fixed-order sum of the per-pair 12-vectors into grad[B][N][6].
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -61,10 +67,24 @@ __device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const T
           gl3 * ((float)h[5] * fc - (float)h[2] * fs);
 }
 
-// Directional derivative of (Ha, Hb, kappa_max) along one motion parameter,
-// contracted with the sensitivities g13 = (dE/dHa [6], dE/dHb [6], dE/dkappa_max).
+constexpr int kSens = 14;  // per-pair sensitivities: dE/dHa [6], dE/dHb [6], two for the arc
+
+// Derivative of a detector arc's end, the zero angle atan2(-A, B) of corner
+// c with A, B the values of the (unscaled) basis lines H there.
+__device__ double arc_end_tangent(const Dual H[6], int corner, double hw, double hh) {
+    const double x = (corner & 2) ? hw : -hw, y = (corner & 1) ? hh : -hh;
+    const double A = H[0].v * x + H[1].v * y + H[2].v, B = H[3].v * x + H[4].v * y + H[5].v;
+    const double dA = H[0].d * x + H[1].d * y + H[2].d, dB = H[3].d * x + H[4].d * y + H[5].d;
+    const double r2 = A * A + B * B;
+    return r2 > 0.0 ? (A * dB - B * dA) / r2 : 0.0;
+}
+
+// Directional derivative of (Ha, Hb, sampled arc) along one motion parameter,
+// contracted with the sensitivities g = (dE/dHa [6], dE/dHb [6], arc [2]):
+// arc = (dE/dkappa_max, 0) for the object-sphere range, (dE/dlo, dE/dhi)
+// for the detector-bounded range.
 __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const ViewGeomGrad &gA,
-                               const ViewGeomGrad &gB, int dir, double R_mm, const float g13[13]) {
+                               const ViewGeomGrad &gB, int dir, const EvalConsts &ec, const float g[kSens]) {
     Dual Pa[12], Pb[12], Ca[3], Cb[3];
     const bool on_a = dir < 6;
     const int q = on_a ? dir : dir - 6;
@@ -77,7 +97,7 @@ __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const View
         Cb[e] = Dual(Bv.C[e], on_a ? 0.0 : gB.dC[q][e]);
     }
     Dual u1[3], u2[3], km;
-    pencil(Ca, Cb, R_mm, u1, u2, km);
+    pencil(Ca, Cb, ec.R_mm, u1, u2, km);
     Dual Ha[6], Hb[6];
     line_map(Pa, Ca, u1, u2, A.u0, A.v0, Ha);
     line_map(Pb, Ca, u1, u2, Bv.u0, Bv.v0, Hb);
@@ -92,10 +112,33 @@ __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const View
     const int ea = ma > 0.0 ? ilogb(ma) : 0, eb = mb > 0.0 ? ilogb(mb) : 0;
     double ga = 0.0, gb = 0.0;
     for (int i = 0; i < 6; ++i) {
-        ga += (double)g13[i] * Ha[i].d;
-        gb += (double)g13[6 + i] * Hb[i].d;
+        ga += (double)g[i] * Ha[i].d;
+        gb += (double)g[6 + i] * Hb[i].d;
     }
-    return ldexp(ga, -ea) + ldexp(gb, -eb) + (double)g13[12] * km.d;
+    double g_arc;
+    if (ec.kappa_detector) {
+        double va[6], vb[6], lo, hi;
+        for (int i = 0; i < 6; ++i) {
+            va[i] = Ha[i].v;
+            vb[i] = Hb[i].v;
+        }
+        ArcEnd e_lo, e_hi;
+        const double hw = (double)ec.half_w, hh = (double)ec.half_h;
+        // d(end): the zero angle of the corner behind it, the mean of both
+        // views' corners at a tie, 0 for a fixed end
+        auto end_tangent = [&](const ArcEnd &e) {
+            const double ta = e.corner_a >= 0 ? arc_end_tangent(Ha, e.corner_a, hw, hh) : 0.0;
+            const double tb = e.corner_b >= 0 ? arc_end_tangent(Hb, e.corner_b, hw, hh) : 0.0;
+            return e.view == 0 ? ta : e.view == 1 ? tb : e.view == 2 ? 0.5 * (ta + tb) : 0.0;
+        };
+        // an empty arc has zero sensitivities (no plane counts)
+        g_arc = pair_arc(va, vb, hw, hh, lo, hi, &e_lo, &e_hi)
+                    ? (double)g[12] * end_tangent(e_lo) + (double)g[13] * end_tangent(e_hi)
+                    : 0.0;
+    } else {
+        g_arc = (double)g[12] * km.d;
+    }
+    return ldexp(ga, -ea) + ldexp(gb, -eb) + g_arc;
 }
 
 // Cost and the pair sensitivities in one sweep over the planes.  With
@@ -123,6 +166,7 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
 
     const Tap *base = (const Tap *)sino;
     const float kinv = 1.0f / (float)ec.K;
+    const bool detector = ec.kappa_detector != 0;
     const bool has_tail = (ec.K & 63) != 0;
     const int n_sweeps = (ec.K >> 6) + (has_tail ? 1 : 0);
     const bool in_tail = lane < (ec.K & 63);
@@ -136,8 +180,8 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         const Tap *sb = base + (int64_t)pc.vb * ec.view_elems;
         float acc = 0.0f;
         int cnt = 0;
-        float g[13];
-        for (int i = 0; i < 13; ++i) g[i] = 0.0f;
+        float g[kSens];
+        for (int i = 0; i < kSens; ++i) g[i] = 0.0f;
         G sn, cs;
         g_sincos(pc.k0 + (G)lane * pc.dk, &sn, &cs);
         for (int i = 0; i < n_sweeps; ++i) {
@@ -155,8 +199,11 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                 float gk = 0.0f;
                 lookup_adjoint<Tap, G>(pc.ha, cs, sn, ta, ec, pc.inv_f2a, pc.sa, diff, ca, g, gk);
                 lookup_adjoint<Tap, G>(pc.hb, cs, sn, tb, ec, pc.inv_f2b, pc.sb, -diff, cb, g + 6, gk);
-                // kappa_k = kappa_max ((2k + 1) / K - 1), k = lane + 64 i
-                g[12] = fmaf(gk, (float)(2 * (lane + 64 * i) + 1) * kinv - 1.0f, g[12]);
+                // object sphere: kappa_k = kappa_max ((2k + 1) / K - 1);
+                // detector arc: kappa_k = lo + u (hi - lo), u = (k + 1/2) / K
+                const float u = ((float)(lane + 64 * i) + 0.5f) * kinv;
+                g[12] = fmaf(gk, detector ? 1.0f - u : 2.0f * u - 1.0f, g[12]);
+                g[13] = fmaf(gk, detector ? u : 0.0f, g[13]);
             }
             const G c2 = cs * pc.rc - sn * pc.rs;
             sn = sn * pc.rc + cs * pc.rs;
@@ -168,10 +215,10 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         const float e = ec.inv_c > 0.0f ? d / den : d;
         wave_acc += (double)e;
         const float coef = cnt > 0 ? 2.0f / ((float)cnt * den * den) : 0.0f;
-        for (int i = 0; i < 13; ++i) g[i] = coef * wave_sum(g[i]);
+        for (int i = 0; i < kSens; ++i) g[i] = coef * wave_sum(g[i]);
         if (lane == 0) {
-            float *out = sens + ((int64_t)hyp * ec.n_pairs + p) * 13;
-            for (int i = 0; i < 13; ++i) out[i] = g[i];
+            float *out = sens + ((int64_t)hyp * ec.n_pairs + p) * kSens;
+            for (int i = 0; i < kSens; ++i) out[i] = g[i];
         }
     }
     if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
@@ -189,9 +236,9 @@ __global__ __launch_bounds__(256) void pair_tangent_kernel(const ViewGeom *__res
     int a, b;
     pair_from_index(hp % ec.n_pairs, ec.n_views, a, b);
     const int64_t ga = (int64_t)hyp * ec.n_views + a, gb = (int64_t)hyp * ec.n_views + b;
-    float g13[13];
-    for (int i = 0; i < 13; ++i) g13[i] = sens[hp * 13 + i];
-    pair_grad[hp * 12 + dir] = (float)pair_tangent(vt[ga], vt[gb], vg[ga], vg[gb], dir, ec.R_mm, g13);
+    float g14[kSens];
+    for (int i = 0; i < kSens; ++i) g14[i] = sens[hp * kSens + i];
+    pair_grad[hp * 12 + dir] = (float)pair_tangent(vt[ga], vt[gb], vg[ga], vg[gb], dir, ec, g14);
 }
 
 template <class Tap, class G>

@@ -132,7 +132,7 @@ Workspace workspace_layout(const Scan *s, int B, bool grad) {
     w.part_off = off;
     off += align256(sizeof(double) * (uint64_t)B * n_tiles_for(s->n_views));
     w.sens_off = off;
-    if (grad) off += align256(sizeof(float) * 13ull * (uint64_t)B * n_pairs);
+    if (grad) off += align256(sizeof(float) * 14ull * (uint64_t)B * n_pairs);  // per-pair sensitivities
     w.pgrad_off = off;
     if (grad) off += align256(sizeof(float) * 12ull * (uint64_t)B * n_pairs);
     w.total = off;
@@ -555,8 +555,6 @@ ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double 
     Scan *s = nullptr;
     ecc_status st;
     if ((st = check_eval(ctx, scan_id, B, params, &s))) return st;
-    if (params->kappa_range != ECC_KAPPA_OBJECT)
-        return fail(ECC_E_ARG, "the gradient is defined for kappa_range ECC_KAPPA_OBJECT only");
     if (!theta_dev || !out_cost_dev || !grad_dev || !workspace_dev) return fail(ECC_E_ARG, "null device pointer");
     const Workspace w = workspace_layout(s, B, true);
     if (workspace_bytes < w.total)

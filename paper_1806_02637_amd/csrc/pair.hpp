@@ -7,6 +7,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "arc.hpp"
 #include "ecc_internal.hpp"
 #include "lookup.hpp"
 #include "projective.hpp"
@@ -23,87 +24,6 @@ __device__ __forceinline__ void pair_from_index(int64_t p, int n, int &a, int &b
     while (aa < n - 2 && pair_index(aa + 1, aa + 2, n) <= p) ++aa;
     a = aa;
     b = (int)(p - pair_index(aa, aa + 1, n)) + aa + 1;
-}
-
-// Arc of plane angles around kappa = 0 whose lines meet the closed detector
-// rectangle |x| <= hw, |y| <= hh (about the principal point), from the
-// centred basis lines H: the line of the plane at kappa is
-// cos(kappa) H[0..2] + sin(kappa) H[3..5].  At corner c the line's value is
-// A_c cos(kappa) + B_c sin(kappa), whose sign changes only at
-// kappa = atan2(-A_c, B_c) mod pi; between consecutive such zeros the
-// meets-the-rectangle decision (corner values not all of one strict sign) is
-// constant, so the arc ends at the first zero, walking away from 0 in each
-// direction, past which an interval misses.  Returns kArcNone when the plane
-// at 0 misses, kArcFull with [-pi/2, pi/2] when every plane meets the
-// rectangle, else kArcPart with the arc (shorter than pi, containing 0).
-enum ArcKind { kArcNone = 0, kArcPart = 1, kArcFull = 2 };
-ECC_HD ArcKind view_arc(const double H[6], double hw, double hh, double &lo, double &hi) {
-    constexpr double kPi = 3.141592653589793;
-    double A[4], Bc[4], z[4];
-    for (int c = 0; c < 4; ++c) {
-        const double x = (c & 2) ? hw : -hw, y = (c & 1) ? hh : -hh;
-        A[c] = H[0] * x + H[1] * y + H[2];
-        Bc[c] = H[3] * x + H[4] * y + H[5];
-    }
-    auto meets = [&](double k) {
-        double sn, cs;
-        sincos(k, &sn, &cs);
-        double mn = A[0] * cs + Bc[0] * sn, mx = mn;
-        for (int c = 1; c < 4; ++c) {
-            const double v = A[c] * cs + Bc[c] * sn;
-            mn = fmin(mn, v);
-            mx = fmax(mx, v);
-        }
-        return mn <= 0.0 && mx >= 0.0;
-    };
-    if (!meets(0.0)) return kArcNone;
-    for (int c = 0; c < 4; ++c) {
-        double w = atan2(-A[c], Bc[c]) + 0.5 * kPi;  // [-pi/2, 3pi/2]
-        if (w >= kPi) w -= kPi;
-        if (w < 0.0) w += kPi;
-        z[c] = w - 0.5 * kPi;  // [-pi/2, pi/2)
-    }
-    // ascending order (four-element sorting network)
-    auto order = [&](int i, int j) {
-        const double a = fmin(z[i], z[j]), b = fmax(z[i], z[j]);
-        z[i] = a;
-        z[j] = b;
-    };
-    order(0, 1);
-    order(2, 3);
-    order(0, 2);
-    order(1, 3);
-    order(1, 2);
-    int n_neg = 0, n_pos = 0;  // zeros below 0, zeros at or below 0
-    for (int c = 0; c < 4; ++c) {
-        n_neg += z[c] < 0.0;
-        n_pos += z[c] <= 0.0;
-    }
-    // upward: the zeros above 0, then those at or below 0 shifted by +pi
-    bool closed = false;
-    double prev = 0.0;
-    for (int j = 0; j < 4 && !closed; ++j) {
-        const int i = n_pos + j;
-        const double k = i < 4 ? z[i] : z[i - 4] + kPi;
-        if (!meets(0.5 * (prev + k))) closed = true;
-        else prev = k;
-    }
-    if (!closed) {
-        lo = -0.5 * kPi;
-        hi = 0.5 * kPi;
-        return kArcFull;
-    }
-    hi = prev;
-    // downward: the zeros below 0, then those at or above 0 shifted by -pi
-    prev = 0.0;
-    for (int j = 0; j < 4; ++j) {
-        const int i = n_neg - 1 - j;
-        const double k = i >= 0 ? z[i] : z[i + 4] - kPi;
-        if (!meets(0.5 * (prev + k))) break;
-        prev = k;
-    }
-    lo = prev;
-    return kArcPart;
 }
 
 // FP64 per-pair geometry -> the per-plane constants of one pair.  The line
@@ -130,18 +50,7 @@ __device__ __forceinline__ void pair_setup(const ViewGeom &A, const ViewGeom &Bv
     }
     double lo = -km, hi = km;
     if (ec.kappa_detector) {
-        const double hw = (double)ec.half_w, hh = (double)ec.half_h;
-        double la, ha_, lb, hb_;
-        const ArcKind ka = view_arc(Ha, hw, hh, la, ha_);
-        const ArcKind kb = ka == kArcNone ? kArcNone : view_arc(Hb, hw, hh, lb, hb_);
-        if (kb != kArcNone) {
-            // a view that sees every plane leaves the other's arc whole (it
-            // may reach past +-pi/2); two partial arcs, each shorter than pi
-            // and containing 0, meet around 0 in [max lows, min highs]
-            const bool full_a = ka == kArcFull, full_b = kb == kArcFull;
-            lo = full_a ? lb : full_b ? la : fmax(la, lb);
-            hi = full_a ? hb_ : full_b ? ha_ : fmin(ha_, hb_);
-        } else {
+        if (!pair_arc(Ha, Hb, (double)ec.half_w, (double)ec.half_h, lo, hi)) {
             // every sample at kappa = 0 on the line x = -2^20 px: off every
             // detector, finite coordinates (clamped cell indices)
             for (int i = 0; i < 6; ++i) Ha[i] = Hb[i] = 0.0;

@@ -348,8 +348,6 @@ ecc_status ecc_server_submit(ecc_server *s, int32_t scan_id, int32_t B, const do
     if (st != ECC_OK) return st;
     if (B < 1 || B > 65536) return ecc::set_error(ECC_E_ARG, "B = %d out of range", B);
     if (params->K < 1 || params->K > 4096) return ecc::set_error(ECC_E_ARG, "K = %d out of range", params->K);
-    if (with_grad && params->kappa_range != ECC_KAPPA_OBJECT)
-        return ecc::set_error(ECC_E_ARG, "the gradient is defined for kappa_range ECC_KAPPA_OBJECT only");
     auto r = std::make_unique<Request>();
     r->scan = scan_id;
     r->B = B;

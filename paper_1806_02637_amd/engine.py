@@ -138,7 +138,7 @@ class Scan:
         return (out, pairs) if with_pairs else out
 
     def cost_grad(self, theta, K: int, R_mm: float, c: float = math.inf, geom: str = "f32",
-                  with_pair_grads: bool = False, workspace: torch.Tensor | None = None):
+                  with_pair_grads: bool = False, workspace: torch.Tensor | None = None, kappa: str = "object"):
         """Returns cost [B] FP64, grad [B, N, 6] FP32 (and per-pair [B, n_pairs, 12])."""
         th = self._theta(theta)
         Bn = th.shape[0]
@@ -147,7 +147,7 @@ class Scan:
         grad = torch.empty((Bn, self.n_views, 6), dtype=torch.float32, device=dev)
         pg = torch.empty((Bn, self.n_pairs, 12), dtype=torch.float32, device=dev) if with_pair_grads else None
         ws = self.workspace(Bn, True) if workspace is None else workspace
-        B.ecc_cost_grad(self.ctx, self.id, Bn, th.data_ptr(), self.params(K, R_mm, c, geom), out.data_ptr(),
+        B.ecc_cost_grad(self.ctx, self.id, Bn, th.data_ptr(), self.params(K, R_mm, c, geom, kappa), out.data_ptr(),
                         grad.data_ptr(), pg.data_ptr() if pg is not None else 0, ws.data_ptr(), ws.numel(),
                         _stream_handle(dev))
         return (out, grad, pg) if with_pair_grads else (out, grad)

@@ -72,14 +72,15 @@ class MotionResult:
 
 def estimate_motion(scan: Scan, K: int, R_mm: float, n_nodes: int = 17, params=(5,), c: float = math.inf,
                     init: np.ndarray | None = None, max_iter: int = 60, gtol: float = 1e-9,
-                    scale: float = 1.0, callback=None) -> MotionResult:
+                    scale: float = 1.0, callback=None, kappa: str = "object") -> MotionResult:
     """Minimises the cost over the spline nodes of the selected parameters
     (indices into theta: 0-2 rotations in degrees, 3-5 translations in mm).
 
     ``scale`` divides the cost seen by the optimiser (the cost's magnitude
     depends on the data; a scale near the initial cost keeps L-BFGS-B's
     tolerances meaningful).  ``init`` gives the starting nodes [6, n_nodes]
-    (zero motion by default)."""
+    (zero motion by default).  ``kappa`` selects the sampled plane range
+    ("object" sphere of radius R_mm, or "detector"-bounded)."""
     from scipy.optimize import minimize
 
     model = SplineMotion(scan, n_nodes)
@@ -95,7 +96,7 @@ def estimate_motion(scan: Scan, K: int, R_mm: float, n_nodes: int = 17, params=(
         t0 = time.perf_counter()
         nodes_dev[0, sel] = torch.as_tensor(x.reshape(len(params), n_nodes), dtype=torch.float64, device=dev)
         th = model.theta(nodes_dev)
-        cost, g_th = scan.cost_grad(th, K, R_mm, c, workspace=ws)
+        cost, g_th = scan.cost_grad(th, K, R_mm, c, workspace=ws, kappa=kappa)
         g_nodes = model.grad(nodes_dev, g_th)
         f = float(cost[0]) / scale
         g = g_nodes[0, sel].reshape(-1).cpu().numpy() / scale
