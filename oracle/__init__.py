@@ -9,7 +9,9 @@ import it; the HIP engine shares no code with it and never calls it.
 
 Modules: ``geometry`` (projective steps), ``sinogram`` (Eq. 1 on a flat
 detector; its inner line integral is plain C in ``sino.c``), ``ecc`` (cost),
-``grad`` (gradient), ``dual`` (forward-mode dual numbers).
+``grad`` (gradient), ``dual`` (forward-mode dual numbers), ``spline`` (the
+Akima motion model), ``fdk`` (the reconstruction a compensated scan is
+checked with).
 """
 from .dual import Dual, ops  # noqa: F401
 from .ecc import EccParams, ecc_cost, ecc_pair, pair_index, pair_list  # noqa: F401
