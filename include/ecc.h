@@ -215,6 +215,45 @@ ecc_status ecc_spline_motion_grad(ecc_ctx *ctx, int32_t B, int32_t n_views, int3
                                   const double *nodes_dev, const float *grad_theta_dev, double *grad_nodes_dev,
                                   void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Reconstruction of a compensated scan (Sec. "Experiments" inspects the
+ * volume reconstructed with the estimated motion): FDK (Feldkamp, Davis and
+ * Kress 1984) for a circular short scan, back-projecting view lam with
+ * P'_lam = P_lam T(theta_lam).  Per view: Parker's short-scan weights
+ * (Parker 1982; fan angle -atan((u - u0) / f), range [0, pi + 2 delta],
+ * delta = (range - pi) / 2) and the cosine weight f / sqrt(f^2 + (u - u0)^2 +
+ * (v - v0)^2), the sampled ramp filter along rows (h(0) = 1/4, h(n) =
+ * -1 / (pi n)^2 for odd n, 0 for even n; Kak and Slaney ch. 3) scaled by
+ * f / D; per voxel x: f(x) = sum over views of dbeta (D / z)^2 Q(u, v) with
+ * (u z, v z, z) = P'_lam (x, 1), bilinear, zero off the detector.  D and the
+ * orbit angles come from the scan's nominal sources; views must be in
+ * increasing orbit angle about +z, evenly spaced (dbeta = range / (N - 1)),
+ * over a range between pi + the full fan angle and 2 pi.  FP32.
+ * ------------------------------------------------------------------------- */
+
+/* Volume: nx x ny x nz voxels (1..4096 each) of voxel_mm, centred on the
+ * isocentre; voxel (i, j, k) at ((i - (nx-1)/2) s, (j - (ny-1)/2) s,
+ * (k - (nz-1)/2) s), stored [nz][ny][nx].  reserved must be 0. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t reserved;
+    double voxel_mm;
+} ecc_volume;
+
+/* Device workspace an ecc_fdk call on this scan needs (the filtered views,
+ * N (H + 1) (W + 2) float pairs, and per-view constants). */
+ecc_status ecc_fdk_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, uint64_t *bytes);
+
+/* Reconstructs into out_dev [nz][ny][nx] FP32 (device, overwritten) from
+ * images_dev [n_views][H][W] FP32 line integrals (device; the scan's own
+ * projections are released once its sinograms exist).  theta_dev [n_views][6]
+ * FP64 (device) is the motion to compensate, NULL for none.  Asynchronous on
+ * `stream`.  Errors: ECC_E_ARG (bad volume, W > 4096, an orbit that is not a
+ * short scan, small workspace), ECC_E_NOSCAN, ECC_E_HIP. */
+ecc_status ecc_fdk(ecc_ctx *ctx, int32_t scan_id, const double *theta_dev, const float *images_dev,
+                   const ecc_volume *vol, float *out_dev, void *workspace_dev, uint64_t workspace_bytes,
+                   void *stream);
+
 
 /* ---------------------------------------------------------------------------
  * Served form: continuous batching of evaluation requests over resident

@@ -77,25 +77,29 @@ def parker_weights(beta: float, gamma: np.ndarray, delta: float) -> np.ndarray:
     return w
 
 
+def filter_row(row, r: int, intr_lam, beta: float, arc_rad: float, sid_mm: float) -> np.ndarray:
+    """One detector row r of one view: Parker and cosine weights, then the
+    ramp filter, Q(u) = (1 / tau) sum_k h(u - k) p_w(k)."""
+    row = np.asarray(row, dtype=np.float64)
+    W = row.shape[0]
+    f, u0, v0 = (float(x) for x in intr_lam)
+    u = np.arange(W) - u0
+    gamma = -np.arctan(u / f)
+    wp = parker_weights(float(beta), gamma, 0.5 * (arc_rad - math.pi))
+    cosw = f / np.sqrt(f * f + u ** 2 + (r - v0) ** 2)
+    tau = sid_mm / f
+    # full linear convolution, then the W outputs aligned with the input
+    return np.convolve(row * cosw * wp, ramp_kernel(W - 1))[W - 1:2 * W - 1] / tau
+
+
 def filter_views(images, intr, betas, arc_rad: float, sid_mm: float) -> np.ndarray:
     """Parker- and cosine-weighted, ramp-filtered projections Q [N, H, W]."""
     imgs = np.asarray(images, dtype=np.float64)
     N, H, W = imgs.shape
-    delta = 0.5 * (arc_rad - math.pi)
-    h = ramp_kernel(W - 1)
     out = np.empty_like(imgs)
     for lam in range(N):
-        f, u0, v0 = (float(x) for x in intr[lam])
-        u = np.arange(W) - u0
-        v = np.arange(H) - v0
-        gamma = -np.arctan(u / f)
-        wp = parker_weights(float(betas[lam]), gamma, delta)
-        cosw = f / np.sqrt(f * f + u[None, :] ** 2 + v[:, None] ** 2)
-        pw = imgs[lam] * cosw * wp[None, :]
-        tau = sid_mm / f
         for r in range(H):
-            # full linear convolution, then the W outputs aligned with the input
-            out[lam, r] = np.convolve(pw[r], h)[W - 1:2 * W - 1] / tau
+            out[lam, r] = filter_row(imgs[lam, r], r, intr[lam], betas[lam], arc_rad, sid_mm)
     return out
 
 
@@ -137,3 +141,41 @@ def fdk(images, P, intr, betas, arc_rad: float, sid_mm: float, vol: Volume, move
     Q = filter_views(images, intr, betas, arc_rad, sid_mm)
     dbeta = arc_rad / (N - 1)
     return backproject(Q, P if moved_P is None else moved_P, vol, dbeta, sid_mm)
+
+
+def voxel_values(points, row_of, shape, P, intr, betas, arc_rad: float, sid_mm: float, moved_P=None):
+    """f at a few points [M, 3] (mm) without filtering every row: the rows a
+    point's bilinear cells need are filtered on first use.  row_of(lam, r)
+    returns image row r of view lam; shape = (N, H, W)."""
+    N, H, W = shape
+    Pm = P if moved_P is None else moved_P
+    dbeta = arc_rad / (N - 1)
+    cache = {}
+
+    def q_row(lam, r):
+        if r < 0 or r >= H:
+            return None
+        key = (lam, r)
+        if key not in cache:
+            cache[key] = filter_row(row_of(lam, r), r, intr[lam], betas[lam], arc_rad, sid_mm)
+        return cache[key]
+
+    out = np.zeros(len(points))
+    for i, x in enumerate(np.asarray(points, dtype=np.float64)):
+        xh = np.append(x, 1.0)
+        for lam in range(N):
+            p = np.asarray(Pm[lam], dtype=np.float64) @ xh
+            depth = p[2]
+            u, v = p[0] / depth, p[1] / depth
+            uf, vf = math.floor(u), math.floor(v)
+            fu, fv = u - uf, v - vf
+            val = 0.0
+            for dv, wv in ((0, 1.0 - fv), (1, fv)):
+                row = q_row(lam, vf + dv)
+                if row is None:
+                    continue
+                for du, wu in ((0, 1.0 - fu), (1, fu)):
+                    if 0 <= uf + du < W:
+                        val += wv * wu * row[uf + du]
+            out[i] += dbeta * (sid_mm / depth) ** 2 * val
+    return out

@@ -25,6 +25,7 @@ SYMBOLS = (
     "ecc_last_error", "ecc_create", "ecc_destroy", "ecc_scan_load", "ecc_scan_build_sinograms",
     "ecc_scan_set_sinograms", "ecc_scan_read_sinogram", "ecc_scan_free", "ecc_scan_bytes", "ecc_workspace_bytes",
     "ecc_cost", "ecc_cost_grad", "ecc_cost_pinv", "ecc_scan_info", "ecc_spline_motion", "ecc_spline_motion_grad",
+    "ecc_fdk_workspace_bytes", "ecc_fdk",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_wait", "ecc_server_request_bytes",
     "ecc_server_set_work_cap", "ecc_server_destroy",
 )
@@ -39,6 +40,11 @@ class EccError(RuntimeError):
 class EvalParams(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("geom", ctypes.c_int32), ("R_mm", ctypes.c_double), ("c", ctypes.c_double),
                 ("kappa_range", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class EccVolume(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("voxel_mm", ctypes.c_double)]
 
 
 class RequestStats(ctypes.Structure):
@@ -68,6 +74,8 @@ _SIGNATURES = {
     "ecc_scan_info": ([_P, _I32] + [ctypes.POINTER(_I32)] * 5, _I32),
     "ecc_spline_motion": ([_P, _I32, _I32, _I32, _P, _P, _P, _P], _I32),
     "ecc_spline_motion_grad": ([_P, _I32, _I32, _I32, _P, _P, _P, _P, _P], _I32),
+    "ecc_fdk_workspace_bytes": ([_P, _I32, ctypes.POINTER(_U64)], _I32),
+    "ecc_fdk": ([_P, _I32, _P, _P, ctypes.POINTER(EccVolume), _P, _P, _U64, _P], _I32),
     "ecc_server_create": ([_P, ctypes.POINTER(_P), _I32, _U64], _I32),
     "ecc_server_submit": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _I32, ctypes.POINTER(ctypes.c_int64)],
                           _I32),
@@ -176,6 +184,18 @@ def ecc_scan_info(ctx: int, scan_id: int):
     vals = [_I32() for _ in range(5)]
     _check(load_library().ecc_scan_info(ctx, scan_id, *[ctypes.byref(v) for v in vals]), "ecc_scan_info")
     return tuple(v.value for v in vals)
+
+
+def ecc_fdk_workspace_bytes(ctx: int, scan_id: int) -> int:
+    out = _U64()
+    _check(load_library().ecc_fdk_workspace_bytes(ctx, scan_id, ctypes.byref(out)), "ecc_fdk_workspace_bytes")
+    return int(out.value)
+
+
+def ecc_fdk(ctx: int, scan_id: int, theta_ptr: int, images_ptr: int, vol: EccVolume, out_ptr: int,
+            workspace_ptr: int, workspace_bytes: int, stream: int = 0):
+    _check(load_library().ecc_fdk(ctx, scan_id, theta_ptr, images_ptr, ctypes.byref(vol), out_ptr, workspace_ptr,
+                                  workspace_bytes, stream), "ecc_fdk")
 
 
 def ecc_spline_motion(ctx: int, B: int, n_views: int, n_nodes: int, node_x_ptr: int, nodes_ptr: int,

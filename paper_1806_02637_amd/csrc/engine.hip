@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/ecc.h"
 #include "ecc_internal.hpp"
@@ -51,6 +52,7 @@ struct Scan {
     void *sino_dev = nullptr;
     float *scale_dev = nullptr;  // [N]
     uint32_t *absmax_dev = nullptr;
+    std::vector<double> P_host, intr_host;  // copies for host-side geometry checks
     SinoLayout layout{};
     double ds_px = 0.0;
     bool built = false;
@@ -269,6 +271,8 @@ ecc_status ecc_scan_load(ecc_ctx *ctx, int32_t *scan_id, int32_t n_views, int32_
     std::lock_guard<std::mutex> lk(ctx->mu);
     Scan *s = new Scan();
     s->n_views = n_views;
+    s->P_host.assign(P, P + 12ull * n_views);
+    s->intr_host.assign(intr, intr + 3ull * n_views);
     s->W = W;
     s->H = H;
     ecc_status st;
@@ -462,6 +466,105 @@ static ecc_status check_spline(ecc_ctx *ctx, int32_t B, int32_t n_views, int32_t
     }
     if (node_x[0] > 0.0 || node_x[n_nodes - 1] < (double)(n_views - 1))
         return fail(ECC_E_ARG, "nodes must cover the views [0, %d]", n_views - 1);
+    return ECC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FDK reconstruction of a compensated scan.
+
+namespace {
+
+struct FdkWorkspace {
+    uint64_t theta_off, nom_off, mov_off, views_off, q_off, total;
+};
+
+FdkWorkspace fdk_workspace_layout(const Scan *s) {
+    FdkWorkspace w{};
+    uint64_t off = 0;
+    w.theta_off = off;
+    off += align256(sizeof(double) * 6ull * s->n_views);
+    w.nom_off = off;
+    off += align256(sizeof(ViewGeom) * (uint64_t)s->n_views);
+    w.mov_off = off;
+    off += align256(sizeof(ViewGeom) * (uint64_t)s->n_views);
+    w.views_off = off;
+    off += align256(sizeof(FdkView) * (uint64_t)s->n_views);
+    w.q_off = off;
+    off += align256(sizeof(float) * 2ull * s->n_views * (s->H + 1) * (uint64_t)(s->W + 2));
+    w.total = off;
+    return w;
+}
+
+// The nominal orbit must be a short scan about the z axis: views in order of
+// increasing orbit angle atan2(C_y, C_x), a range between pi + the fan angle
+// and 2 pi (Parker's weights need the range to cover every ray once).
+ecc_status check_fdk_orbit(const Scan *s) {
+    const int n = s->n_views;
+    double b0 = 0.0, prev = -1.0, fan = 0.0;
+    for (int v = 0; v < n; ++v) {
+        const double *p = s->P_host.data() + 12 * v;
+        // source: the null vector of P, C = -M^{-1} p4 (Cramer's rule)
+        const double a = p[0], b = p[1], c = p[2], d = p[4], e = p[5], f = p[6], g = p[8], h = p[9], i = p[10];
+        const double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+        const double r0 = -p[3], r1 = -p[7], r2 = -p[11];
+        const double cx = (r0 * (e * i - f * h) - b * (r1 * i - f * r2) + c * (r1 * h - e * r2)) / det;
+        const double cy = (a * (r1 * i - f * r2) - r0 * (d * i - f * g) + c * (d * r2 - r1 * g)) / det;
+        double beta = atan2(cy, cx);
+        if (v == 0) b0 = beta;
+        beta = fmod(beta - b0, 2.0 * M_PI);
+        if (beta < 0.0) beta += 2.0 * M_PI;
+        if (v > 0 && !(beta > prev)) return fail(ECC_E_ARG, "FDK needs views in increasing orbit angle (view %d)", v);
+        prev = beta;
+        const double fpx = s->intr_host[3 * v], u0 = s->intr_host[3 * v + 1];
+        fan = fmax(fan, fmax(fabs(atan(u0 / fpx)), fabs(atan((s->W - 1 - u0) / fpx))));
+    }
+    if (!(prev > M_PI + 2.0 * fan) || !(prev < 2.0 * M_PI))
+        return fail(ECC_E_ARG, "orbit range %.4f rad is not a short scan (needs pi + %.4f rad, less than 2 pi)", prev,
+                    2.0 * fan);
+    return ECC_OK;
+}
+
+}  // namespace
+
+ecc_status ecc_fdk_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, uint64_t *bytes) {
+    if (!ctx || !bytes) return fail(ECC_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    *bytes = fdk_workspace_layout(s).total;
+    return ECC_OK;
+}
+
+ecc_status ecc_fdk(ecc_ctx *ctx, int32_t scan_id, const double *theta_dev, const float *images_dev,
+                   const ecc_volume *vol, float *out_dev, void *workspace_dev, uint64_t workspace_bytes,
+                   void *stream) {
+    if (!ctx || !vol || !images_dev || !out_dev || !workspace_dev) return fail(ECC_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Scan *s = find_scan(ctx, scan_id);
+    if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+    if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1 || vol->nx > 4096 || vol->ny > 4096 || vol->nz > 4096)
+        return fail(ECC_E_ARG, "volume %dx%dx%d out of range [1, 4096]", vol->nx, vol->ny, vol->nz);
+    if (!(vol->voxel_mm > 0.0) || !isfinite(vol->voxel_mm)) return fail(ECC_E_ARG, "voxel_mm must be positive");
+    if (vol->reserved != 0) return fail(ECC_E_ARG, "reserved field must be 0");
+    if (s->W > 4096) return fail(ECC_E_ARG, "FDK filters rows of at most 4096 pixels (W = %d)", s->W);
+    ecc_status st;
+    if ((st = check_fdk_orbit(s))) return st;
+    const FdkWorkspace w = fdk_workspace_layout(s);
+    if (workspace_bytes < w.total)
+        return fail(ECC_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
+                    (unsigned long long)workspace_bytes, (unsigned long long)w.total);
+    DeviceGuard g(ctx->device);
+    hipStream_t hs = (hipStream_t)stream;
+    char *ws = (char *)workspace_dev;
+    double *zero = (double *)(ws + w.theta_off);
+    ViewGeom *nom = (ViewGeom *)(ws + w.nom_off);
+    ViewGeom *mov = (ViewGeom *)(ws + w.mov_off);
+    HIP_TRY(hipMemsetAsync(zero, 0, sizeof(double) * 6ull * s->n_views, hs));
+    HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, zero, 1, s->n_views, nom, nullptr, hs));
+    if (theta_dev) HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, 1, s->n_views, mov, nullptr, hs));
+    const FdkVolume fv{vol->nx, vol->ny, vol->nz, (float)vol->voxel_mm};
+    HIP_TRY(launch_fdk(images_dev, nom, theta_dev ? mov : nom, s->n_views, s->W, s->H, fv,
+                       (FdkView *)(ws + w.views_off), (float2 *)(ws + w.q_off), out_dev, hs));
     return ECC_OK;
 }
 

@@ -64,6 +64,7 @@ class Scan:
         self.n_pairs = n_views * (n_views - 1) // 2
         self.n_alpha = self.n_t = None
         self._ws = {}
+        self._fdk_ws = None
 
     @property
     def ctx(self):
@@ -96,6 +97,7 @@ class Scan:
 
     def free(self):
         B.ecc_scan_free(self.ctx, self.id)
+        self._fdk_ws = None
 
     def workspace(self, Bn: int, with_grad: bool) -> torch.Tensor:
         key = (Bn, bool(with_grad))
@@ -136,6 +138,30 @@ class Scan:
                    pairs.data_ptr() if pairs is not None else 0, ws.data_ptr(), ws.numel(),
                    _stream_handle(self.engine.device))
         return (out, pairs) if with_pairs else out
+
+    def fdk(self, images, vol, theta=None) -> torch.Tensor:
+        """FDK reconstruction [nz, ny, nx] (FP32 device tensor) of this scan's
+        geometry from line-integral images [N, H, W] (FP32, device); vol =
+        (nx, ny, nz, voxel_mm) centred on the isocentre; theta [N, 6] the
+        motion to compensate (back-projection with P T(theta)), None for
+        none."""
+        dev = self.engine.device
+        imgs = torch.as_tensor(images, dtype=torch.float32, device=dev).contiguous()
+        if tuple(imgs.shape) != (self.n_views, self.H, self.W):
+            raise ValueError(f"images must be [{self.n_views}, {self.H}, {self.W}], got {tuple(imgs.shape)}")
+        nx, ny, nz, vox = vol
+        th = None
+        if theta is not None:
+            th = torch.as_tensor(theta, dtype=torch.float64, device=dev).reshape(self.n_views, 6).contiguous()
+        out = torch.empty((int(nz), int(ny), int(nx)), dtype=torch.float32, device=dev)
+        nbytes = B.ecc_fdk_workspace_bytes(self.ctx, self.id)
+        if self._fdk_ws is None or self._fdk_ws.numel() < nbytes:
+            self._fdk_ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        ws = self._fdk_ws
+        B.ecc_fdk(self.ctx, self.id, th.data_ptr() if th is not None else 0, imgs.data_ptr(),
+                  B.EccVolume(int(nx), int(ny), int(nz), 0, float(vox)), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                  _stream_handle(dev))
+        return out
 
     def cost_grad(self, theta, K: int, R_mm: float, c: float = math.inf, geom: str = "f32",
                   with_pair_grads: bool = False, workspace: torch.Tensor | None = None, kappa: str = "object"):

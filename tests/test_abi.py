@@ -49,6 +49,15 @@ def test_status_codes_and_eval_params_layout(tmp_path):
     E = binding.EvalParams
     py_layout = [ctypes.sizeof(E)] + [getattr(E, f).offset for f in ("K", "geom", "R_mm", "c", "kappa_range", "reserved")]
     assert c_layout == py_layout
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "ecc.h"\n'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ecc_volume), offsetof(ecc_volume, nx),'
+        ' offsetof(ecc_volume, ny), offsetof(ecc_volume, nz), offsetof(ecc_volume, reserved),'
+        ' offsetof(ecc_volume, voxel_mm)); return 0; }\n')
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    c_layout = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    V = binding.EccVolume
+    assert c_layout == [ctypes.sizeof(V)] + [getattr(V, f).offset for f in ("nx", "ny", "nz", "reserved", "voxel_mm")]
     assert (binding.ECC_KAPPA_OBJECT, binding.ECC_KAPPA_DETECTOR) == (0, 1)
     assert (binding.ECC_OK, binding.ECC_E_ARG, binding.ECC_E_BUDGET, binding.ECC_E_HIP, binding.ECC_E_STATE,
             binding.ECC_E_NOSCAN) == (0, -1, -2, -3, -4, -5)
