@@ -69,22 +69,6 @@ struct EvalConsts {
     double t0_d, inv_dt_d, inv_dalpha_d;
 };
 
-// Per-view constants of the FDK reconstruction (FP32).
-struct FdkView {
-    float P[12];              // moved P' = P T(theta), rows 0-1 about the principal point
-    float beta, delta;        // orbit angle from the first view; (scan range - pi) / 2
-    float f, u0, v0;          // intrinsics (pixels)
-    float scale, inv_tau;     // dbeta D^2; f / D (1 / pixel pitch at the isocentre)
-    float pad;
-};
-static_assert(sizeof(FdkView) == 80, "FdkView layout");
-
-// Reconstruction grid: nx x ny x nz voxels of voxel_mm centred on the isocentre.
-struct FdkVolume {
-    int32_t nx, ny, nz;
-    float voxel_mm;
-};
-
 // Pair index <-> (a, b), a < b, row-major triangle.
 __host__ __device__ inline int64_t pair_index(int a, int b, int n) {
     return (int64_t)a * n - (int64_t)a * (a + 1) / 2 + (b - a - 1);
@@ -106,8 +90,6 @@ hipError_t launch_view_setup(const double *P, const double *intr, const double *
 size_t pair_const_bytes(bool geom64);
 // pinv (optional): [B][n_views][4][3] pseudo-inverses of the moved P' (the
 // line route the method replaces)
-hipError_t launch_fdk(const float *images, const ViewGeom *nominal, const ViewGeom *moved, int n_views, int W,
-                      int H, FdkVolume vol, FdkView *views, float2 *Qi, float *out, hipStream_t s);
 hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s,
                              const double *pinv = nullptr);
 hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,

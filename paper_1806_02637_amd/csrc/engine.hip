@@ -16,6 +16,7 @@
 
 #include "../../include/ecc.h"
 #include "ecc_internal.hpp"
+#include "fdk.hpp"
 
 using namespace ecc;
 
@@ -490,7 +491,7 @@ FdkWorkspace fdk_workspace_layout(const Scan *s) {
     w.views_off = off;
     off += align256(sizeof(FdkView) * (uint64_t)s->n_views);
     w.q_off = off;
-    off += align256(sizeof(float) * 2ull * s->n_views * (s->H + 1) * (uint64_t)(s->W + 2));
+    off += align256(sizeof(float) * 2ull * s->n_views * (s->H + 3) * (uint64_t)(s->W + 4));
     w.total = off;
     return w;
 }

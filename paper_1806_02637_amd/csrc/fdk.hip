@@ -9,18 +9,22 @@
 //                weight (Parker 1982) and the cosine weight applied while the
 //                row is staged in LDS, then the sampled ramp filter (Kak and
 //                Slaney, ch. 3: h(0) = 1/4, h(n) = -1/(pi n)^2 for odd n) as a
-//                direct sum over the odd taps, written as interleaved row pairs
-//                so one 16-byte load returns a bilinear cell.
+//                direct sum over the odd taps (8 outputs per thread sharing
+//                sliding register windows), scaled by dbeta D^2 and written
+//                as interleaved row pairs inside a two-wide zero border, so one
+//                16-byte load returns a bilinear cell.
 // fdk_backproject  16 x 16 voxel columns x 16 slices per workgroup; each
 //                thread walks one column's 16 voxels through every view:
 //                (a, b, c) = P' (x, 1) with rows 0-1 about the principal
-//                point, (u, v) = (u0, v0) + (a, b) / c, weight dbeta D^2 / c^2,
-//                bilinear read of the filtered view.
+//                point, (u, v) = (u0, v0) + (a, b) / c, weight 1 / c^2,
+//                bilinear read of the filtered view (clamped into its zero
+//                border off the detector).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
 #include "ecc_internal.hpp"
+#include "fdk.hpp"
 
 namespace ecc {
 
@@ -81,54 +85,137 @@ __device__ __forceinline__ float parker(float beta, float gamma, float delta) {
     return 1.0f;
 }
 
-// Dynamic LDS: xs[3W] (the weighted row between two W-long zero margins) and
-// hs[W/2 + 1] (the odd ramp taps h(2m + 1)).
-__global__ __launch_bounds__(256) void fdk_filter_kernel(const float *__restrict__ images,
-                                                         const FdkView *__restrict__ views, int W, int H,
-                                                         float2 *__restrict__ Qi) {
+// Ramp filter of one thread's outputs: the 8 outputs u0, u0 + 2, ..., u0 + 14
+// (one parity), Q(u) = x(u) / 4 + sum_m h_m (x(u - n_m) + x(u + n_m)) over the
+// odd taps n_m = 2m + 1.  With L_i = x(u0 - 1 - 2i) and R_i = x(u0 + 1 + 2i),
+// output j takes L_{m - j} and R_{m + j} at tap m, so two windows of 15
+// values slide by 8 taps per chunk: 16 new reads feed 64 tap pairs.  xc: the
+// row with zero margins of at least W + 64 on both sides; hs: M8 taps (a
+// multiple of 8, zero past the last odd tap).
+constexpr int kFiltOut = 8;
+__host__ __device__ inline void filter_group(const float *xc, const float *hs, int M8, int u0, float acc[kFiltOut]) {
+    float Lw[15], Rw[15];
+#pragma unroll
+    for (int t = 0; t < 15; ++t) {
+        Lw[t] = xc[u0 - 1 - 2 * (t - 7)];  // L_{t - 7}
+        Rw[t] = xc[u0 + 1 + 2 * t];        // R_t
+    }
+#pragma unroll
+    for (int j = 0; j < kFiltOut; ++j) acc[j] = 0.25f * xc[u0 + 2 * j];
+    for (int c = 0; c < M8; c += 8) {
+        float h[8], nL[8], nR[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) h[i] = hs[c + i];
+        // the next chunk's new window values, read before this chunk's sums
+        // so that the reads overlap them
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            nL[t] = xc[u0 - 1 - 2 * (c + 8 + t)];   // L_{c + 8 + t}
+            nR[t] = xc[u0 + 1 + 2 * (c + 15 + t)];  // R_{c + 15 + t}
+        }
+        // Lw[t] = L_{c - 7 + t}, Rw[t] = R_{c + t}
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) {
+#pragma unroll
+            for (int j = 0; j < kFiltOut; ++j) acc[j] = fmaf(h[mm], Lw[mm - j + 7] + Rw[mm + j], acc[j]);
+        }
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            Lw[t] = Lw[t + 8];
+            Rw[t] = Rw[t + 8];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            Lw[7 + t] = nL[t];
+            Rw[7 + t] = nR[t];
+        }
+    }
+}
+
+// Filter workgroups: `rows` (1 or 2) consecutive detector rows of one view
+// per workgroup (two rows give more active lanes per wave than one row of
+// ceil(W / 8) work items), 2 ceil(W / 16) threads per row (rounded up to
+// whole waves over the workgroup), thread 2g + p of a row taking outputs
+// 16 g + p + 2 j.  Dynamic LDS per row: the weighted row with W + 64 zeros
+// on each side; then the taps, padded to a multiple of 8.
+__host__ __device__ inline int filter_margin(int W) { return W + 64; }
+__host__ __device__ inline int filter_taps8(int W) { return ((W / 2 + 7) / 8) * 8; }
+__host__ __device__ inline int filter_row_floats(int W) { return 2 * filter_margin(W) + W; }
+__host__ __device__ inline int filter_items(int W) { return 2 * ((W + 15) / 16); }
+
+__global__ __launch_bounds__(1024) void fdk_filter_kernel(const float *__restrict__ images,
+                                                          const FdkView *__restrict__ views, int W, int H, int rows,
+                                                          float2 *__restrict__ Qi) {
     extern __shared__ float sm[];
-    float *xs = sm;
-    float *hs = sm + 3 * W;
-    const int v = blockIdx.x, view = blockIdx.y;
+    const int pad = filter_margin(W), M8 = filter_taps8(W), RF = filter_row_floats(W);
+    float *hs = sm + rows * RF;  // [M8]
+    const int view = blockIdx.y, v_first = blockIdx.x * rows;
+    const int n_rows = min(rows, H - v_first);
     const FdkView vw = views[view];
-    const float *row = images + ((int64_t)view * H + v) * W;
-    const float dv = (float)v - vw.v0;
-    const float f2 = vw.f * vw.f + dv * dv;
-    for (int k = threadIdx.x; k < W; k += blockDim.x) {
-        const float du = (float)k - vw.u0;
-        const float cosw = vw.f * rsqrtf(f2 + du * du);
-        const float gamma = -atanf(du / vw.f);
-        xs[W + k] = row[k] * cosw * parker(vw.beta, gamma, vw.delta);
-        xs[k] = 0.0f;
-        xs[2 * W + k] = 0.0f;
+    for (int r = 0; r < n_rows; ++r) {
+        float *xs = sm + r * RF;
+        const int v = v_first + r;
+        const float *row = images + ((int64_t)view * H + v) * W;
+        const float dv = (float)v - vw.v0;
+        const float f2 = vw.f * vw.f + dv * dv;
+        for (int k = threadIdx.x; k < W; k += blockDim.x) {
+            const float du = (float)k - vw.u0;
+            const float cosw = vw.f * rsqrtf(f2 + du * du);
+            const float gamma = -atanf(du / vw.f);
+            xs[pad + k] = row[k] * cosw * parker(vw.beta, gamma, vw.delta);
+        }
+        for (int k = threadIdx.x; k < pad; k += blockDim.x) {
+            xs[k] = 0.0f;
+            xs[pad + W + k] = 0.0f;
+        }
     }
     const int M = W / 2;  // odd taps n = 2m + 1 <= W - 1
-    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    for (int m = threadIdx.x; m < M8; m += blockDim.x) {
         const float n = (float)(2 * m + 1);
-        hs[m] = -1.0f / (kPiF * kPiF * n * n);
+        hs[m] = m < M ? -1.0f / (kPiF * kPiF * n * n) : 0.0f;
     }
     __syncthreads();
-    // interleaved row pairs: Qi[r][c] = (Q[r - 1][c - 1], Q[r][c - 1]) for
-    // r = 0..H, c = 0..W + 1, zero beyond the detector
-    float2 *pair_lo = Qi + ((int64_t)view * (H + 1) + (v + 1)) * (W + 2);  // .x of row pair (v, v + 1)
-    float2 *pair_hi = Qi + ((int64_t)view * (H + 1) + v) * (W + 2);        // .y of row pair (v - 1, v)
-    for (int c = threadIdx.x; c < W + 2; c += blockDim.x) {
-        float q = 0.0f;
-        const int u = c - 1;
-        if (u >= 0 && u < W) {
-            const float *xu = xs + W + u;
-            float acc = 0.25f * xu[0];
-#pragma unroll 4
-            for (int m = 0; m < M; ++m) {
-                const int n = 2 * m + 1;
-                acc = fmaf(hs[m], xu[-n] + xu[n], acc);
+    // padded grid Qp[v + 2][u + 2] = dbeta D^2 Q[v][u], two zero rows and
+    // columns on every side, stored as interleaved row pairs
+    // Qi[r][c] = (Qp[r][c], Qp[r + 1][c]), r = 0..H + 2, c = 0..W + 3
+    const int WP = W + 4, items = filter_items(W);
+    const float out_scale = vw.inv_tau * vw.scale;
+    const int r = threadIdx.x / items, item = threadIdx.x % items;
+    const int v = v_first + r;
+    if (r < n_rows) {
+        float2 *row_x = Qi + ((int64_t)view * (H + 3) + (v + 2)) * WP;  // .x of pair r = v + 2
+        float2 *row_y = Qi + ((int64_t)view * (H + 3) + (v + 1)) * WP;  // .y of pair r = v + 1
+        const int g = item >> 1, u0 = 16 * g + (item & 1);
+        if (16 * g < W) {
+            float acc[kFiltOut];
+            filter_group(sm + r * RF + pad, hs, M8, u0, acc);
+#pragma unroll
+            for (int j = 0; j < kFiltOut; ++j) {
+                const int u = u0 + 2 * j;
+                if (u < W) {
+                    row_x[u + 2].x = acc[j] * out_scale;
+                    row_y[u + 2].y = acc[j] * out_scale;
+                }
             }
-            q = acc * vw.inv_tau;
         }
-        pair_lo[c].x = q;
-        pair_hi[c].y = q;
-        if (v == 0) (pair_lo - (W + 2))[c].x = 0.0f;  // row pair (-1, 0)
-        if (v == H - 1) (pair_lo)[c].y = 0.0f;        // row pair (H - 1, H)
+        if (item < 4) {  // zero columns 0, 1, W + 2, W + 3
+            const int c = item < 2 ? item : W + item;
+            row_x[c].x = 0.0f;
+            row_y[c].y = 0.0f;
+        }
+    }
+    for (int c = threadIdx.x; c < WP; c += blockDim.x) {
+        float2 *first = Qi + ((int64_t)view * (H + 3)) * WP;
+        if (v_first == 0) {  // zero rows Qp[0], Qp[1]
+            first[c].x = 0.0f;
+            first[c].y = 0.0f;
+            first[WP + c].x = 0.0f;
+        }
+        if (v_first + n_rows == H) {  // zero rows Qp[H + 2], Qp[H + 3]
+            first[(int64_t)(H + 1) * WP + c].y = 0.0f;
+            first[(int64_t)(H + 2) * WP + c].x = 0.0f;
+            first[(int64_t)(H + 2) * WP + c].y = 0.0f;
+        }
     }
 }
 
@@ -136,18 +223,32 @@ constexpr int kBpTile = 16;   // voxel columns per workgroup side
 constexpr int kBpSlab = 16;   // slices per thread
 constexpr int kBpStage = 128;  // views staged in LDS at a time
 
+// Workgroups are numbered so that each XCD (8 per chip, blocks dealt to them
+// round-robin) takes one contiguous range of tiles, x fastest then y then z:
+// a z-slab of the volume, whose footprint in every view is a band of rows
+// that fits the XCD's L2.
 __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__restrict__ Qi,
                                                               const FdkView *__restrict__ views, int n_views,
-                                                              int W, int H, FdkVolume vol, float *__restrict__ out) {
+                                                              int W, int H, FdkVolume vol, int tiles_x, int tiles_y,
+                                                              int n_tiles, float *__restrict__ out) {
     __shared__ FdkView sv[kBpStage];
-    const int ix = blockIdx.x * kBpTile + (threadIdx.x % kBpTile);
-    const int iy = blockIdx.y * kBpTile + (threadIdx.x / kBpTile);
-    const int iz0 = blockIdx.z * kBpSlab;
+    const int per = (n_tiles + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (tile >= n_tiles) return;  // no barrier has been reached yet
+    const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
+    // each wave takes an 8 x 8 quarter of the 16 x 16 tile: its 64 voxel
+    // columns project onto a compact detector patch (few cache lines per gather)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ix = tx * kBpTile + (wave & 1) * 8 + (lane & 7);
+    const int iy = ty * kBpTile + (wave >> 1) * 8 + (lane >> 3);
+    const int iz0 = tz * kBpSlab;
     const float s = vol.voxel_mm;
     const float x = ((float)ix - 0.5f * (float)(vol.nx - 1)) * s;
     const float y = ((float)iy - 0.5f * (float)(vol.ny - 1)) * s;
     const float z0 = ((float)iz0 - 0.5f * (float)(vol.nz - 1)) * s;
-    const int64_t view_elems = (int64_t)(H + 1) * (W + 2);
+    const uint32_t WP = (uint32_t)W + 4;
+    const int64_t view_bytes = (int64_t)(H + 3) * WP * sizeof(float2);
+    const float u_hi = (float)W, v_hi = (float)H;
     float acc[kBpSlab];
 #pragma unroll
     for (int k = 0; k < kBpSlab; ++k) acc[k] = 0.0f;
@@ -162,27 +263,27 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
             const float b0 = fmaf(w.P[4], x, fmaf(w.P[5], y, fmaf(w.P[6], z0, w.P[7])));
             const float c0 = fmaf(w.P[8], x, fmaf(w.P[9], y, fmaf(w.P[10], z0, w.P[11])));
             const float da = w.P[2] * s, db = w.P[6] * s, dc = w.P[10] * s;
-            const float2 *q = Qi + (int64_t)(v0 + j) * view_elems;
+            const char *q = (const char *)Qi + (int64_t)(v0 + j) * view_bytes;
 #pragma unroll
             for (int k = 0; k < kBpSlab; ++k) {
                 const float a = fmaf((float)k, da, a0);
                 const float b = fmaf((float)k, db, b0);
                 const float c = fmaf((float)k, dc, c0);
-                const float rc = __builtin_amdgcn_rcpf(c);
+                // a point behind the source counts zero (rc = 0 also keeps
+                // its coordinates finite)
+                const float rc = c > 0.0f ? __builtin_amdgcn_rcpf(c) : 0.0f;
                 const float u = fmaf(a, rc, w.u0), vv = fmaf(b, rc, w.v0);
-                const float uf = floorf(u), vf = floorf(vv);
+                // cells off the detector are clamped into the two-wide zero
+                // border: any point outside reads four zeros
+                const float uf = __builtin_amdgcn_fmed3f(floorf(u), -2.0f, u_hi);
+                const float vf = __builtin_amdgcn_fmed3f(floorf(vv), -2.0f, v_hi);
                 const float fu = u - uf, fv = vv - vf;
-                // cells with a corner on the detector; others read a clamped
-                // cell and count zero
-                const bool ok = (c > 0.0f) & (uf >= -1.0f) & (uf <= (float)(W - 1)) & (vf >= -1.0f) &
-                                (vf <= (float)(H - 1));
-                const int iu = (int)fminf(fmaxf(uf, -1.0f), (float)(W - 1));
-                const int iv = (int)fminf(fmaxf(vf, -1.0f), (float)(H - 1));
-                const fdk_f32x4_a8 t = *(const fdk_f32x4_a8 *)(q + (int64_t)(iv + 1) * (W + 2) + (iu + 1));
+                const uint32_t e = __umul24((uint32_t)((int)vf + 2), WP) + (uint32_t)((int)uf + 2);
+                const fdk_f32x4_a8 t = *(const fdk_f32x4_a8 *)(q + e * (uint32_t)sizeof(float2));
                 const float top = fmaf(fu, t.z - t.x, t.x);
                 const float bot = fmaf(fu, t.w - t.y, t.y);
                 const float val = fmaf(fv, bot - top, top);
-                acc[k] = ok ? fmaf(w.scale * rc * rc, val, acc[k]) : acc[k];
+                acc[k] = fmaf(rc * rc, val, acc[k]);
             }
         }
     }
@@ -200,14 +301,18 @@ hipError_t launch_fdk(const float *images, const ViewGeom *nominal, const ViewGe
                        views);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = sizeof(float) * (3 * (size_t)W + W / 2 + 1);
-    hipLaunchKernelGGL(fdk_filter_kernel, dim3(H, n_views), dim3(256), lds, s, images, (const FdkView *)views, W, H,
-                       Qi);
+    // two rows per workgroup while they fit 64 KB of LDS
+    const size_t row_bytes = sizeof(float) * filter_row_floats(W), tap_bytes = sizeof(float) * filter_taps8(W);
+    const int rows = 2 * row_bytes + tap_bytes <= 65536 ? 2 : 1;
+    const int threads = 64 * ((rows * filter_items(W) + 63) / 64);
+    hipLaunchKernelGGL(fdk_filter_kernel, dim3((H + rows - 1) / rows, n_views), dim3(threads), rows * row_bytes + tap_bytes,
+                       s, images, (const FdkView *)views, W, H, rows, Qi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const dim3 grid((vol.nx + kBpTile - 1) / kBpTile, (vol.ny + kBpTile - 1) / kBpTile,
-                    (vol.nz + kBpSlab - 1) / kBpSlab);
-    hipLaunchKernelGGL(fdk_backproject_kernel, grid, dim3(kBpTile * kBpTile), 0, s, (const float2 *)Qi,
-                       (const FdkView *)views, n_views, W, H, vol, out);
+    const int tiles_x = (vol.nx + kBpTile - 1) / kBpTile, tiles_y = (vol.ny + kBpTile - 1) / kBpTile;
+    const int n_tiles = tiles_x * tiles_y * ((vol.nz + kBpSlab - 1) / kBpSlab);
+    const int blocks = 8 * ((n_tiles + 7) / 8);
+    hipLaunchKernelGGL(fdk_backproject_kernel, dim3(blocks), dim3(kBpTile * kBpTile), 0, s, (const float2 *)Qi,
+                       (const FdkView *)views, n_views, W, H, vol, tiles_x, tiles_y, n_tiles, out);
     return hipGetLastError();
 }
 

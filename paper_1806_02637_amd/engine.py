@@ -163,6 +163,10 @@ class Scan:
                   _stream_handle(dev))
         return out
 
+    def release_fdk_workspace(self):
+        """Drops the cached FDK workspace (the filtered views)."""
+        self._fdk_ws = None
+
     def cost_grad(self, theta, K: int, R_mm: float, c: float = math.inf, geom: str = "f32",
                   with_pair_grads: bool = False, workspace: torch.Tensor | None = None, kappa: str = "object"):
         """Returns cost [B] FP64, grad [B, N, 6] FP32 (and per-pair [B, n_pairs, 12])."""
