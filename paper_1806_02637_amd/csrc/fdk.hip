@@ -5,13 +5,14 @@
 //
 // fdk_view       one thread per view: orbit angle from the nominal source,
 //                angular step, source distance D, and the moved P' in FP32.
-// fdk_filter     one workgroup per (view, detector row): Parker's short-scan
-//                weight (Parker 1982) and the cosine weight applied while the
-//                row is staged in LDS, then the sampled ramp filter (Kak and
-//                Slaney, ch. 3: h(0) = 1/4, h(n) = -1/(pi n)^2 for odd n) as a
-//                direct sum over the odd taps (8 outputs per thread sharing
-//                sliding register windows), scaled by dbeta D^2 and written
-//                as interleaved row pairs inside a two-wide zero border, so one
+// fdk_parker     Parker's short-scan weight (Parker 1982) of every (view,
+//                column).
+// fdk_filter_mfma  the sampled ramp filter (Kak and Slaney, ch. 3: h(0) = 1/4,
+//                h(n) = -1/(pi n)^2 for odd n) of every cosine- and
+//                Parker-weighted detector row, as two Toeplitz matrix products
+//                on the matrix cores (one per output-column parity), scaled by
+//                dbeta D^2 and written as interleaved row pairs inside a
+//                two-wide zero border (fdk_border writes the border), so one
 //                16-byte load returns a bilinear cell.
 // fdk_backproject  16 x 16 voxel columns x 16 slices per workgroup; each
 //                thread walks one column's 16 voxels through every view:
@@ -85,138 +86,144 @@ __device__ __forceinline__ float parker(float beta, float gamma, float delta) {
     return 1.0f;
 }
 
-// Ramp filter of one thread's outputs: the 8 outputs u0, u0 + 2, ..., u0 + 14
-// (one parity), Q(u) = x(u) / 4 + sum_m h_m (x(u - n_m) + x(u + n_m)) over the
-// odd taps n_m = 2m + 1.  With L_i = x(u0 - 1 - 2i) and R_i = x(u0 + 1 + 2i),
-// output j takes L_{m - j} and R_{m + j} at tap m, so two windows of 15
-// values slide by 8 taps per chunk: 16 new reads feed 64 tap pairs.  xc: the
-// row with zero margins of at least W + 64 on both sides; hs: M8 taps (a
-// multiple of 8, zero past the last odd tap).
-constexpr int kFiltOut = 8;
-__host__ __device__ inline void filter_group(const float *xc, const float *hs, int M8, int u0, float acc[kFiltOut]) {
-    float Lw[15], Rw[15];
-#pragma unroll
-    for (int t = 0; t < 15; ++t) {
-        Lw[t] = xc[u0 - 1 - 2 * (t - 7)];  // L_{t - 7}
-        Rw[t] = xc[u0 + 1 + 2 * t];        // R_t
+// ---------------------------------------------------------------------------
+// The ramp filter as a matrix product on the matrix cores.  Split the outputs
+// by column parity p, u = 2i + p.  The filter's off-diagonal taps are odd,
+// so they pair each output with the inputs of the other parity,
+// k = 2j + 1 - p, and u - k = 2(i - j) + 2p - 1: per parity
+// Q_p = X_q G_p + X_p / 4 with the Toeplitz G_p[j][i] = h(2(i - j) + 2p - 1).
+// The rows of X are all detector rows of all views, so each parity is one
+// (N H) x (W / 2) x (W / 2) FP32 product (v_mfma_f32_32x32x2f32), half the
+// multiply-adds of the plain convolution.  A (weighted inputs) is staged in
+// LDS per 32-input step; B is read from the 1-D table of G_p's diagonals.
+
+typedef float fdk_v16f __attribute__((ext_vector_type(16)));
+
+constexpr int kMmRows = 64;   // detector rows per workgroup (2 waves of 32)
+constexpr int kMmCols = 128;  // outputs of one parity per workgroup (2 waves of 2 x 32)
+constexpr int kMmK = 32;      // inputs staged per step
+
+// Parker weight of every (view, column).
+__global__ __launch_bounds__(256) void fdk_parker_kernel(const FdkView *__restrict__ views, int n_views, int W,
+                                                         float *__restrict__ pw) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_views * W) return;
+    const FdkView vw = views[idx / W];
+    const float du = (float)(idx % W) - vw.u0;
+    pw[idx] = parker(vw.beta, -atanf(du / vw.f), vw.delta);
+}
+
+// Weighted input x(r, k) = p(r, k) * cosine weight * Parker weight.
+__device__ __forceinline__ float weighted_input(const float *__restrict__ images, const float *__restrict__ pw,
+                                                const FdkView &vw, int view, int v, int64_t r, int k, int W) {
+    const float du = (float)k - vw.u0, dv = (float)v - vw.v0;
+    const float cosw = vw.f * rsqrtf(vw.f * vw.f + du * du + dv * dv);
+    return images[r * W + k] * cosw * pw[(int64_t)view * W + k];
+}
+
+// Workgroups: (parity, row tile, column tile), numbered with the column tile
+// fastest and dealt so that each XCD takes a contiguous range: the column
+// tiles of one row tile share its inputs in the XCD's L2.  Dynamic LDS: the
+// diagonals of G_p, W - 1 floats.
+__global__ __launch_bounds__(256) void fdk_filter_mfma_kernel(const float *__restrict__ images,
+                                                              const FdkView *__restrict__ views,
+                                                              const float *__restrict__ pw, int n_views, int W,
+                                                              int H, int row_tiles, int col_tiles,
+                                                              float2 *__restrict__ Qi) {
+    __shared__ float As[kMmRows][kMmK + 1];
+    extern __shared__ float gs[];
+    const int total = 2 * row_tiles * col_tiles;
+    const int per = (total + 7) / 8;
+    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (t >= total) return;  // before any barrier
+    const int p = t / (row_tiles * col_tiles), rem = t % (row_tiles * col_tiles);
+    const int row_tile = rem / col_tiles, col_tile = rem % col_tiles;
+    const int q = 1 - p;
+    const int Wp = (W + 1 - p) / 2, Wq = (W + 1 - q) / 2;  // outputs of parity p, inputs of parity q
+    const int64_t n_rows = (int64_t)n_views * H;
+    // g[d + Wq - 1] = h(2d + 2p - 1), d = i - j in [-(Wq - 1), Wp - 1]
+    for (int e = threadIdx.x; e < Wp + Wq - 1; e += blockDim.x) {
+        const float n = (float)(2 * (e - (Wq - 1)) + 2 * p - 1);
+        gs[e] = -1.0f / (kPiF * kPiF * n * n);
     }
-#pragma unroll
-    for (int j = 0; j < kFiltOut; ++j) acc[j] = 0.25f * xc[u0 + 2 * j];
-    for (int c = 0; c < M8; c += 8) {
-        float h[8], nL[8], nR[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) h[i] = hs[c + i];
-        // the next chunk's new window values, read before this chunk's sums
-        // so that the reads overlap them
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            nL[t] = xc[u0 - 1 - 2 * (c + 8 + t)];   // L_{c + 8 + t}
-            nR[t] = xc[u0 + 1 + 2 * (c + 15 + t)];  // R_{c + 15 + t}
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int64_t r_base = (int64_t)row_tile * kMmRows;
+    const int i_base = col_tile * kMmCols + 64 * wc;
+    fdk_v16f acc0 = {0}, acc1 = {0};
+    for (int j0 = 0; j0 < Wq; j0 += kMmK) {
+        __syncthreads();  // the previous step's reads of As are done (and gs is written)
+        for (int e = threadIdx.x; e < kMmRows * kMmK; e += blockDim.x) {
+            const int rr = e / kMmK, jj = e % kMmK;
+            const int64_t r = r_base + rr;
+            const int j = j0 + jj;
+            float val = 0.0f;
+            if (r < n_rows && j < Wq) {
+                const int view = (int)(r / H), v = (int)(r % H);
+                val = weighted_input(images, pw, views[view], view, v, r, 2 * j + q, W);
+            }
+            As[rr][jj] = val;
         }
-        // Lw[t] = L_{c - 7 + t}, Rw[t] = R_{c + t}
-#pragma unroll
-        for (int mm = 0; mm < 8; ++mm) {
-#pragma unroll
-            for (int j = 0; j < kFiltOut; ++j) acc[j] = fmaf(h[mm], Lw[mm - j + 7] + Rw[mm + j], acc[j]);
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kMmK; kk += 2) {
+            const float a = As[32 * wr + (lane & 31)][kk + (lane >> 5)];
+            const int j = j0 + kk + (lane >> 5);
+            const int i0 = i_base + (lane & 31), i1 = i0 + 32;
+            const bool jok = j < Wq;
+            const float b0 = (jok && i0 < Wp) ? gs[i0 - j + Wq - 1] : 0.0f;
+            const float b1 = (jok && i1 < Wp) ? gs[i1 - j + Wq - 1] : 0.0f;
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
         }
+    }
+    // outputs: register e of lane l holds row 8 (e / 4) + 4 (l / 32) + e % 4,
+    // column l % 32 of the wave's 32 x 32 block
+    const int WP = W + 4;
 #pragma unroll
-        for (int t = 0; t < 7; ++t) {
-            Lw[t] = Lw[t + 8];
-            Rw[t] = Rw[t + 8];
-        }
+    for (int e = 0; e < 16; ++e) {
+        const int64_t r = r_base + 32 * wr + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
+        if (r >= n_rows) continue;
+        const int view = (int)(r / H), v = (int)(r % H);
+        const FdkView &vw = views[view];
+        const float out_scale = vw.inv_tau * vw.scale;
+        float2 *row_x = Qi + ((int64_t)view * (H + 3) + (v + 2)) * WP;
+        float2 *row_y = Qi + ((int64_t)view * (H + 3) + (v + 1)) * WP;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            Lw[7 + t] = nL[t];
-            Rw[7 + t] = nR[t];
+        for (int h = 0; h < 2; ++h) {
+            const int i = (h == 0 ? i_base : i_base + 32) + (lane & 31);
+            if (i >= Wp) continue;
+            const int u = 2 * i + p;
+            const float acc = h == 0 ? acc0[e] : acc1[e];
+            const float qv = (acc + 0.25f * weighted_input(images, pw, vw, view, v, r, u, W)) * out_scale;
+            row_x[u + 2].x = qv;
+            row_y[u + 2].y = qv;
         }
     }
 }
 
-// Filter workgroups: `rows` (1 or 2) consecutive detector rows of one view
-// per workgroup (two rows give more active lanes per wave than one row of
-// ceil(W / 8) work items), 2 ceil(W / 16) threads per row (rounded up to
-// whole waves over the workgroup), thread 2g + p of a row taking outputs
-// 16 g + p + 2 j.  Dynamic LDS per row: the weighted row with W + 64 zeros
-// on each side; then the taps, padded to a multiple of 8.
-__host__ __device__ inline int filter_margin(int W) { return W + 64; }
-__host__ __device__ inline int filter_taps8(int W) { return ((W / 2 + 7) / 8) * 8; }
-__host__ __device__ inline int filter_row_floats(int W) { return 2 * filter_margin(W) + W; }
-__host__ __device__ inline int filter_items(int W) { return 2 * ((W + 15) / 16); }
-
-__global__ __launch_bounds__(1024) void fdk_filter_kernel(const float *__restrict__ images,
-                                                          const FdkView *__restrict__ views, int W, int H, int rows,
-                                                          float2 *__restrict__ Qi) {
-    extern __shared__ float sm[];
-    const int pad = filter_margin(W), M8 = filter_taps8(W), RF = filter_row_floats(W);
-    float *hs = sm + rows * RF;  // [M8]
-    const int view = blockIdx.y, v_first = blockIdx.x * rows;
-    const int n_rows = min(rows, H - v_first);
-    const FdkView vw = views[view];
-    for (int r = 0; r < n_rows; ++r) {
-        float *xs = sm + r * RF;
-        const int v = v_first + r;
-        const float *row = images + ((int64_t)view * H + v) * W;
-        const float dv = (float)v - vw.v0;
-        const float f2 = vw.f * vw.f + dv * dv;
-        for (int k = threadIdx.x; k < W; k += blockDim.x) {
-            const float du = (float)k - vw.u0;
-            const float cosw = vw.f * rsqrtf(f2 + du * du);
-            const float gamma = -atanf(du / vw.f);
-            xs[pad + k] = row[k] * cosw * parker(vw.beta, gamma, vw.delta);
-        }
-        for (int k = threadIdx.x; k < pad; k += blockDim.x) {
-            xs[k] = 0.0f;
-            xs[pad + W + k] = 0.0f;
-        }
+// The zero border of the interleaved filtered views: columns 0, 1, W + 2,
+// W + 3 of every row pair, and the pair halves that hold rows Qp[0], Qp[1],
+// Qp[H + 2], Qp[H + 3].
+__global__ __launch_bounds__(256) void fdk_border_kernel(int n_views, int W, int H, float2 *__restrict__ Qi) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int WP = W + 4;
+    const int64_t n_cols = (int64_t)n_views * (H + 3) * 4;
+    if (idx < n_cols) {
+        const int64_t vr = idx / 4;  // view * (H + 3) + r
+        const int c = (int)(idx % 4);
+        Qi[vr * WP + (c < 2 ? c : W + c)] = make_float2(0.0f, 0.0f);
+        return;
     }
-    const int M = W / 2;  // odd taps n = 2m + 1 <= W - 1
-    for (int m = threadIdx.x; m < M8; m += blockDim.x) {
-        const float n = (float)(2 * m + 1);
-        hs[m] = m < M ? -1.0f / (kPiF * kPiF * n * n) : 0.0f;
-    }
-    __syncthreads();
-    // padded grid Qp[v + 2][u + 2] = dbeta D^2 Q[v][u], two zero rows and
-    // columns on every side, stored as interleaved row pairs
-    // Qi[r][c] = (Qp[r][c], Qp[r + 1][c]), r = 0..H + 2, c = 0..W + 3
-    const int WP = W + 4, items = filter_items(W);
-    const float out_scale = vw.inv_tau * vw.scale;
-    const int r = threadIdx.x / items, item = threadIdx.x % items;
-    const int v = v_first + r;
-    if (r < n_rows) {
-        float2 *row_x = Qi + ((int64_t)view * (H + 3) + (v + 2)) * WP;  // .x of pair r = v + 2
-        float2 *row_y = Qi + ((int64_t)view * (H + 3) + (v + 1)) * WP;  // .y of pair r = v + 1
-        const int g = item >> 1, u0 = 16 * g + (item & 1);
-        if (16 * g < W) {
-            float acc[kFiltOut];
-            filter_group(sm + r * RF + pad, hs, M8, u0, acc);
-#pragma unroll
-            for (int j = 0; j < kFiltOut; ++j) {
-                const int u = u0 + 2 * j;
-                if (u < W) {
-                    row_x[u + 2].x = acc[j] * out_scale;
-                    row_y[u + 2].y = acc[j] * out_scale;
-                }
-            }
-        }
-        if (item < 4) {  // zero columns 0, 1, W + 2, W + 3
-            const int c = item < 2 ? item : W + item;
-            row_x[c].x = 0.0f;
-            row_y[c].y = 0.0f;
-        }
-    }
-    for (int c = threadIdx.x; c < WP; c += blockDim.x) {
-        float2 *first = Qi + ((int64_t)view * (H + 3)) * WP;
-        if (v_first == 0) {  // zero rows Qp[0], Qp[1]
-            first[c].x = 0.0f;
-            first[c].y = 0.0f;
-            first[WP + c].x = 0.0f;
-        }
-        if (v_first + n_rows == H) {  // zero rows Qp[H + 2], Qp[H + 3]
-            first[(int64_t)(H + 1) * WP + c].y = 0.0f;
-            first[(int64_t)(H + 2) * WP + c].x = 0.0f;
-            first[(int64_t)(H + 2) * WP + c].y = 0.0f;
-        }
-    }
+    const int64_t k = idx - n_cols;
+    if (k >= (int64_t)n_views * W) return;
+    const int64_t view = k / W;
+    const int c = (int)(k % W) + 2;
+    float2 *base = Qi + view * (H + 3) * WP;
+    base[c] = make_float2(0.0f, 0.0f);                        // pair 0: Qp[0], Qp[1]
+    base[WP + c].x = 0.0f;                                     // pair 1: Qp[1]
+    base[(int64_t)(H + 1) * WP + c].y = 0.0f;                  // pair H + 1: Qp[H + 2]
+    base[(int64_t)(H + 2) * WP + c] = make_float2(0.0f, 0.0f);  // pair H + 2: Qp[H + 2], Qp[H + 3]
 }
 
 constexpr int kBpTile = 16;   // voxel columns per workgroup side
@@ -296,17 +303,25 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
 }
 
 hipError_t launch_fdk(const float *images, const ViewGeom *nominal, const ViewGeom *moved, int n_views, int W,
-                      int H, FdkVolume vol, FdkView *views, float2 *Qi, float *out, hipStream_t s) {
+                      int H, FdkVolume vol, FdkView *views, float *pw, float2 *Qi, float *out, hipStream_t s) {
     hipLaunchKernelGGL(fdk_view_kernel, dim3((n_views + 255) / 256), dim3(256), 0, s, nominal, moved, n_views,
                        views);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // two rows per workgroup while they fit 64 KB of LDS
-    const size_t row_bytes = sizeof(float) * filter_row_floats(W), tap_bytes = sizeof(float) * filter_taps8(W);
-    const int rows = 2 * row_bytes + tap_bytes <= 65536 ? 2 : 1;
-    const int threads = 64 * ((rows * filter_items(W) + 63) / 64);
-    hipLaunchKernelGGL(fdk_filter_kernel, dim3((H + rows - 1) / rows, n_views), dim3(threads), rows * row_bytes + tap_bytes,
-                       s, images, (const FdkView *)views, W, H, rows, Qi);
+    const int64_t n_pw = (int64_t)n_views * W;
+    hipLaunchKernelGGL(fdk_parker_kernel, dim3((unsigned)((n_pw + 255) / 256)), dim3(256), 0, s,
+                       (const FdkView *)views, n_views, W, pw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t n_border = (int64_t)n_views * (H + 3) * 4 + n_pw;
+    hipLaunchKernelGGL(fdk_border_kernel, dim3((unsigned)((n_border + 255) / 256)), dim3(256), 0, s, n_views, W, H,
+                       Qi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int row_tiles = (int)(((int64_t)n_views * H + kMmRows - 1) / kMmRows);
+    const int col_tiles = ((W + 1) / 2 + kMmCols - 1) / kMmCols;
+    const int total = 2 * row_tiles * col_tiles;
+    hipLaunchKernelGGL(fdk_filter_mfma_kernel, dim3((unsigned)(8 * ((total + 7) / 8))), dim3(256),
+                       sizeof(float) * W, s, images, (const FdkView *)views, (const float *)pw, n_views, W, H,
+                       row_tiles, col_tiles, Qi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int tiles_x = (vol.nx + kBpTile - 1) / kBpTile, tiles_y = (vol.ny + kBpTile - 1) / kBpTile;
     const int n_tiles = tiles_x * tiles_y * ((vol.nz + kBpSlab - 1) / kBpSlab);
