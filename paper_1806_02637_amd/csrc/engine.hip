@@ -504,6 +504,7 @@ FdkWorkspace fdk_workspace_layout(const Scan *s) {
 ecc_status check_fdk_orbit(const Scan *s) {
     const int n = s->n_views;
     double b0 = 0.0, prev = -1.0, fan = 0.0;
+    std::vector<double> betas(n);
     for (int v = 0; v < n; ++v) {
         const double *p = s->P_host.data() + 12 * v;
         // source: the null vector of P, C = -M^{-1} p4 (Cramer's rule)
@@ -518,12 +519,19 @@ ecc_status check_fdk_orbit(const Scan *s) {
         if (beta < 0.0) beta += 2.0 * M_PI;
         if (v > 0 && !(beta > prev)) return fail(ECC_E_ARG, "FDK needs views in increasing orbit angle (view %d)", v);
         prev = beta;
+        betas[v] = beta;
         const double fpx = s->intr_host[3 * v], u0 = s->intr_host[3 * v + 1];
         fan = fmax(fan, fmax(fabs(atan(u0 / fpx)), fabs(atan((s->W - 1 - u0) / fpx))));
     }
     if (!(prev > M_PI + 2.0 * fan) || !(prev < 2.0 * M_PI))
         return fail(ECC_E_ARG, "orbit range %.4f rad is not a short scan (needs pi + %.4f rad, less than 2 pi)", prev,
                     2.0 * fan);
+    // the back-projection weighs every view by the same step range / (N - 1)
+    const double step = prev / (n - 1);
+    for (int v = 0; v < n; ++v)
+        if (fabs(betas[v] - v * step) > 0.01 * step)
+            return fail(ECC_E_ARG, "FDK needs evenly spaced views (view %d is %.3g steps off)", v,
+                        (betas[v] - v * step) / step);
     return ECC_OK;
 }
 

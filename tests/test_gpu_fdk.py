@@ -151,3 +151,16 @@ def test_fdk_argument_errors(eng):
                   ws2.data_ptr(), ws2.numel(), 0)
     assert ei.value.status == B.ECC_E_ARG and "short scan" in B.ecc_last_error()
     scan2.free()
+    # one view moved by half an angular step along the orbit: not evenly spaced
+    P3 = g.projection_matrices().copy()
+    half = 0.5 * math.radians(g.arc_deg) / (g.n_views - 1)
+    Rz = np.array([[math.cos(half), -math.sin(half), 0, 0], [math.sin(half), math.cos(half), 0, 0], [0, 0, 1, 0],
+                   [0, 0, 0, 1.0]])
+    P3[7] = P3[7] @ Rz.T
+    scan3 = eng.load_scan(P3, g.intrinsics(), imgs)
+    ws3 = torch.empty(B.ecc_fdk_workspace_bytes(scan3.ctx, scan3.id), dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.EccError) as ei:
+        B.ecc_fdk(scan3.ctx, scan3.id, 0, imgs.data_ptr(), B.EccVolume(2, 2, 2, 0, 1.0), out.data_ptr(),
+                  ws3.data_ptr(), ws3.numel(), 0)
+    assert ei.value.status == B.ECC_E_ARG and "evenly spaced" in B.ecc_last_error()
+    scan3.free()
