@@ -151,3 +151,36 @@ def test_autograd_function(eng, small16):
         c2 = ecc_cost(th, scan, s["w"].K, s["w"].R_mm)
     assert torch.equal(c2, cost.detach())
     scan.free()
+
+
+@pytest.mark.parametrize("dtype,geom", [("f32", "f64"), ("bf16", "f32"), ("bf16", "f64"), ("f16", "f32"),
+                                        ("f16", "f64")])
+def test_gradient_precision_forms_small16(eng, small16, dtype, geom):
+    """The adjoint of the other precision forms: FP64 plane geometry, and
+    BF16 / FP16 storage checked against the oracle evaluated on the stored
+    (decoded) sinograms, so the storage rounding is part of both sides.  With
+    FP64 geometry nothing but FP32 arithmetic separates the two (bar 1e-5);
+    with FP32 geometry a plane whose hit test flips moves the gradient by
+    about 1e-4 (the FP32-geometry bar of 2e-4; these hypotheses are the
+    FP32-storage test's)."""
+    _say(f"case: adjoint small16 dtype={dtype} geom={geom}")
+    s = small16
+    g = s["geom"]
+    scan = eng.load_scan(s["P"], s["intr"], s["images"])
+    scan.set_sinograms(s["sino"].data.astype(np.float32), dtype)
+    stored = np.stack([scan.read_sinogram(v) for v in range(g.n_views)]).astype(np.float64)
+    sino = oracle.FullSinograms(stored, s["grid"])
+    thetas = inputs.random_motion(1001, 2, g.n_views)
+    params = s["params"]
+    cost, grad = scan.cost_grad(thetas, params.K, params.R_mm, geom=geom)
+    cost_f = scan.cost(thetas, params.K, params.R_mm, geom=geom)
+    assert np.allclose(cost.cpu().numpy(), cost_f.cpu().numpy(), rtol=1e-6, atol=0)
+    grad = grad.cpu().numpy()
+    bar = 1e-5 if geom == "f64" else 2e-4
+    for h in range(thetas.shape[0]):
+        c_ref, g_ref, _ = oracle.ecc_grad(s["P"], s["intr"], thetas[h], s["grid"], sino, params)
+        assert abs(float(cost[h]) - c_ref) <= 1e-5 * abs(c_ref)
+        err = np.linalg.norm(grad[h] - g_ref) / np.linalg.norm(g_ref)
+        _say(f"  hyp {h}: cost {float(cost[h]):.6e} vs {c_ref:.6e}, grad rel L2 {err:.2e}")
+        assert err <= bar
+    scan.free()
