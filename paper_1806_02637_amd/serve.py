@@ -50,12 +50,12 @@ class Server:
         return B.ecc_server_request_bytes(self.srv, scan.id, Bn, int(with_grad))
 
     def submit(self, scan: Scan, theta, K: int, R_mm: float, with_grad: bool = False, c: float = math.inf,
-               geom: str = "f32") -> int:
+               geom: str = "f32", kappa: str = "object") -> int:
         th = np.ascontiguousarray(theta, dtype=np.float64)
         if th.ndim == 2:
             th = th[None]
-        rid = B.ecc_server_submit(self.srv, scan.id, th.shape[0], th.ctypes.data, Scan.params(K, R_mm, c, geom),
-                                  int(with_grad))
+        rid = B.ecc_server_submit(self.srv, scan.id, th.shape[0], th.ctypes.data,
+                                  Scan.params(K, R_mm, c, geom, kappa), int(with_grad))
         with self._lock:
             self._meta[rid] = (th.shape[0], scan.n_views, bool(with_grad))
         return rid

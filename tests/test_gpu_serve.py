@@ -182,3 +182,29 @@ def test_work_cap_admission(served):
         binding.ecc_server_set_work_cap(srv.srv, -1.0)
     assert ei.value.status == binding.ECC_E_ARG
     srv.close()
+
+
+def test_detector_range_requests(served):
+    """Requests with the detector-bounded plane range (cost and gradient)
+    served in a mix with object-range requests: each result equals the
+    direct call's."""
+    from paper_1806_02637_amd.serve import Server
+
+    _say("case: serve detector-range requests in a mix")
+    eng, scans = served
+    srv = Server(eng, n_slots=4, arena_bytes=1 << 30)
+    jobs = []
+    for i, (sc, g, K, R) in enumerate(scans[:4]):
+        th = inputs.random_motion(40 + i, 4, g.n_views)
+        for kappa in ("detector", "object"):
+            for grad in (False, True):
+                jobs.append((srv.submit(sc, th, K, R, with_grad=grad, kappa=kappa), sc, th, K, R, kappa, grad))
+    for rid, sc, th, K, R, kappa, grad in jobs:
+        r = srv.wait(rid)
+        if grad:
+            c0, g0 = sc.cost_grad(th, K, R, kappa=kappa)
+            assert np.array_equal(r.grad, g0.cpu().numpy())
+        else:
+            c0 = sc.cost(th, K, R, kappa=kappa)
+        assert np.array_equal(r.cost, c0.cpu().numpy())
+    srv.close()
