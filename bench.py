@@ -347,6 +347,16 @@ def measure_motion_estimation(eng, max_iter=60):
            "tz_rms_error_mm": {"start": float(np.sqrt(np.mean(ref ** 2))),
                                "end": float(np.sqrt(np.mean((est - ref) ** 2)))},
            "note": "errors after removing the common offset, which the cost cannot observe"}
+    # the other reading of the sampled plane range, from the same start
+    res_d = estimate_motion(scan, K=w.K, R_mm=w.R_mm, n_nodes=cfg["n_nodes"], params=cfg["params"],
+                            max_iter=max_iter, kappa="detector")
+    est_d = res_d.theta[:, p] - res_d.theta[:, p].mean()
+    out["detector_range"] = {"iterations": res_d.n_iter, "evaluations": res_d.n_evals, "seconds": res_d.seconds,
+                             "ms_per_evaluation_median": float(np.median(res_d.eval_ms)),
+                             "cost_start": res_d.cost0, "cost_end": res_d.cost,
+                             "cost_at_truth": float(scan.cost(truth[None], w.K, w.R_mm, kappa="detector")[0]),
+                             "tz_rms_error_mm_end": float(np.sqrt(np.mean((est_d - ref) ** 2))),
+                             "note": "planes sample the arc both detectors see instead of the object sphere's"}
     # the check the paper makes: reconstructions of the moving scan without and
     # with the estimated motion (its unobservable common offset set to the
     # truth's) against the reconstruction of the same object scanned at rest

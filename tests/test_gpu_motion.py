@@ -74,16 +74,18 @@ def test_spline_argument_errors(eng):
     del g
 
 
-def test_motion_estimation_recovers_drift(eng):
+@pytest.mark.parametrize("kappa", ["object", "detector"])
+def test_motion_estimation_recovers_drift(eng, kappa):
     """A 96-view scan (620x480 detector at 0.616 mm) of an FOV-contained
     phantom drifting along z (2 mm peak): L-BFGS over 9 Akima nodes of t_z
     lowers the cost by orders of magnitude and recovers the drift (up to the
-    common offset, which the cost cannot see) to a fraction of a pixel."""
+    common offset, which the cost cannot see) to a fraction of a pixel, with
+    either reading of the sampled plane range."""
     import torch
 
     from paper_1806_02637_amd.motion import estimate_motion
 
-    _say("case: motion estimation 96 views, 9 t_z nodes")
+    _say(f"case: motion estimation 96 views, 9 t_z nodes, {kappa} range")
     g = inputs.ScanGeometry(96, 620, 480, 0.616)
     truth = inputs.smooth_motion(21, g.n_views, peak=2.0, params=(5,))
     phantom = inputs.random_phantom(2, 30, contained_radius=0.95 * g.fov_radius())
@@ -93,8 +95,8 @@ def test_motion_estimation_recovers_drift(eng):
     del imgs
     torch.cuda.empty_cache()
     R = g.default_object_radius()
-    c_true = float(scan.cost(truth[None], 256, R)[0])
-    res = estimate_motion(scan, K=256, R_mm=R, n_nodes=9, params=(5,), max_iter=80)
+    c_true = float(scan.cost(truth[None], 256, R, kappa=kappa)[0])
+    res = estimate_motion(scan, K=256, R_mm=R, n_nodes=9, params=(5,), max_iter=80, kappa=kappa)
     err0 = truth[:, 5] - truth[:, 5].mean()
     est = res.theta[:, 5] - res.theta[:, 5].mean()
     rms0, rms = float(np.sqrt(np.mean(err0 ** 2))), float(np.sqrt(np.mean((est - err0) ** 2)))
