@@ -240,8 +240,9 @@ typedef struct {
     double voxel_mm;
 } ecc_volume;
 
-/* Device workspace an ecc_fdk call on this scan needs (the filtered views,
- * N (H + 3) (W + 4) float pairs, and per-view constants). */
+/* Device workspace an ecc_fdk call on this scan needs (the weighted rows,
+ * N H W floats, the filtered views, N (H + 3) (W + 4) float pairs, and
+ * per-view constants). */
 ecc_status ecc_fdk_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, uint64_t *bytes);
 
 /* Reconstructs into out_dev [nz][ny][nx] FP32 (device, overwritten) from

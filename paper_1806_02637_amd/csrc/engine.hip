@@ -476,7 +476,7 @@ static ecc_status check_spline(ecc_ctx *ctx, int32_t B, int32_t n_views, int32_t
 namespace {
 
 struct FdkWorkspace {
-    uint64_t theta_off, nom_off, mov_off, views_off, pw_off, q_off, total;
+    uint64_t theta_off, nom_off, mov_off, views_off, pw_off, xw_off, q_off, total;
 };
 
 FdkWorkspace fdk_workspace_layout(const Scan *s) {
@@ -492,6 +492,8 @@ FdkWorkspace fdk_workspace_layout(const Scan *s) {
     off += align256(sizeof(FdkView) * (uint64_t)s->n_views);
     w.pw_off = off;
     off += align256(sizeof(float) * (uint64_t)s->n_views * s->W);
+    w.xw_off = off;
+    off += align256(sizeof(float) * (uint64_t)s->n_views * s->H * s->W);
     w.q_off = off;
     off += align256(sizeof(float) * 2ull * s->n_views * (s->H + 3) * (uint64_t)(s->W + 4));
     w.total = off;
@@ -575,8 +577,8 @@ ecc_status ecc_fdk(ecc_ctx *ctx, int32_t scan_id, const double *theta_dev, const
     if (theta_dev) HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, 1, s->n_views, mov, nullptr, hs));
     const FdkVolume fv{vol->nx, vol->ny, vol->nz, (float)vol->voxel_mm};
     HIP_TRY(launch_fdk(images_dev, nom, theta_dev ? mov : nom, s->n_views, s->W, s->H, fv,
-                       (FdkView *)(ws + w.views_off), (float *)(ws + w.pw_off), (float2 *)(ws + w.q_off), out_dev,
-                       hs));
+                       (FdkView *)(ws + w.views_off), (float *)(ws + w.pw_off), (float *)(ws + w.xw_off),
+                       (float2 *)(ws + w.q_off), out_dev, hs));
     return ECC_OK;
 }
 

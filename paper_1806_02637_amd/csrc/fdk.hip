@@ -7,9 +7,11 @@
 //                angular step, source distance D, and the moved P' in FP32.
 // fdk_parker     Parker's short-scan weight (Parker 1982) of every (view,
 //                column).
+// fdk_weight     cosine- and Parker-weighted detector rows, split by column
+//                parity.
 // fdk_filter_mfma  the sampled ramp filter (Kak and Slaney, ch. 3: h(0) = 1/4,
-//                h(n) = -1/(pi n)^2 for odd n) of every cosine- and
-//                Parker-weighted detector row, as two Toeplitz matrix products
+//                h(n) = -1/(pi n)^2 for odd n) of every weighted detector
+//                row, as two Toeplitz matrix products
 //                on the matrix cores (one per output-column parity), scaled by
 //                dbeta D^2 and written as interleaved row pairs inside a
 //                two-wide zero border (fdk_border writes the border), so one
@@ -113,21 +115,33 @@ __global__ __launch_bounds__(256) void fdk_parker_kernel(const FdkView *__restri
     pw[idx] = parker(vw.beta, -atanf(du / vw.f), vw.delta);
 }
 
-// Weighted input x(r, k) = p(r, k) * cosine weight * Parker weight.
-__device__ __forceinline__ float weighted_input(const float *__restrict__ images, const float *__restrict__ pw,
-                                                const FdkView &vw, int view, int v, int64_t r, int k, int W) {
+// Weighted inputs x(r, k) = p(r, k) * cosine weight * Parker weight, split by
+// column parity: X_even[r][j] = x(r, 2j) ([N H][ceil(W / 2)]) and
+// X_odd[r][j] = x(r, 2j + 1) ([N H][floor(W / 2)]), so the products read
+// contiguous rows.
+__global__ __launch_bounds__(256) void fdk_weight_kernel(const float *__restrict__ images,
+                                                         const FdkView *__restrict__ views,
+                                                         const float *__restrict__ pw, int W, int H,
+                                                         float *__restrict__ x_even, float *__restrict__ x_odd) {
+    const int k = blockIdx.y * blockDim.x + threadIdx.x;
+    const int64_t r = blockIdx.x;  // view * H + v
+    if (k >= W) return;
+    const int view = (int)(r / H), v = (int)(r % H);
+    const FdkView vw = views[view];
     const float du = (float)k - vw.u0, dv = (float)v - vw.v0;
     const float cosw = vw.f * rsqrtf(vw.f * vw.f + du * du + dv * dv);
-    return images[r * W + k] * cosw * pw[(int64_t)view * W + k];
+    const float x = images[r * W + k] * cosw * pw[(int64_t)view * W + k];
+    if (k & 1) x_odd[r * (W / 2) + (k >> 1)] = x;
+    else x_even[r * ((W + 1) / 2) + (k >> 1)] = x;
 }
 
 // Workgroups: (parity, row tile, column tile), numbered with the column tile
 // fastest and dealt so that each XCD takes a contiguous range: the column
 // tiles of one row tile share its inputs in the XCD's L2.  Dynamic LDS: the
 // diagonals of G_p, W - 1 floats.
-__global__ __launch_bounds__(256) void fdk_filter_mfma_kernel(const float *__restrict__ images,
-                                                              const FdkView *__restrict__ views,
-                                                              const float *__restrict__ pw, int n_views, int W,
+__global__ __launch_bounds__(256) void fdk_filter_mfma_kernel(const float *__restrict__ x_even,
+                                                              const float *__restrict__ x_odd,
+                                                              const FdkView *__restrict__ views, int n_views, int W,
                                                               int H, int row_tiles, int col_tiles,
                                                               float2 *__restrict__ Qi) {
     __shared__ float As[kMmRows][kMmK + 1];
@@ -141,6 +155,8 @@ __global__ __launch_bounds__(256) void fdk_filter_mfma_kernel(const float *__res
     const int q = 1 - p;
     const int Wp = (W + 1 - p) / 2, Wq = (W + 1 - q) / 2;  // outputs of parity p, inputs of parity q
     const int64_t n_rows = (int64_t)n_views * H;
+    const float *xq = q ? x_odd : x_even;  // [n_rows][Wq]
+    const float *xp = p ? x_odd : x_even;  // [n_rows][Wp]
     // g[d + Wq - 1] = h(2d + 2p - 1), d = i - j in [-(Wq - 1), Wp - 1]
     for (int e = threadIdx.x; e < Wp + Wq - 1; e += blockDim.x) {
         const float n = (float)(2 * (e - (Wq - 1)) + 2 * p - 1);
@@ -151,20 +167,29 @@ __global__ __launch_bounds__(256) void fdk_filter_mfma_kernel(const float *__res
     const int64_t r_base = (int64_t)row_tile * kMmRows;
     const int i_base = col_tile * kMmCols + 64 * wc;
     fdk_v16f acc0 = {0}, acc1 = {0};
+    // each thread stages 8 inputs of a step; the next step's are loaded into
+    // registers while this step's products run
+    constexpr int kPer = kMmRows * kMmK / 256;
+    float pre[kPer];
+    auto load_step = [&](int j0) {
+#pragma unroll
+        for (int e8 = 0; e8 < kPer; ++e8) {
+            const int e = threadIdx.x + 256 * e8;
+            const int64_t r = r_base + e / kMmK;
+            const int j = j0 + e % kMmK;
+            pre[e8] = (r < n_rows && j < Wq) ? xq[r * Wq + j] : 0.0f;
+        }
+    };
+    load_step(0);
     for (int j0 = 0; j0 < Wq; j0 += kMmK) {
         __syncthreads();  // the previous step's reads of As are done (and gs is written)
-        for (int e = threadIdx.x; e < kMmRows * kMmK; e += blockDim.x) {
-            const int rr = e / kMmK, jj = e % kMmK;
-            const int64_t r = r_base + rr;
-            const int j = j0 + jj;
-            float val = 0.0f;
-            if (r < n_rows && j < Wq) {
-                const int view = (int)(r / H), v = (int)(r % H);
-                val = weighted_input(images, pw, views[view], view, v, r, 2 * j + q, W);
-            }
-            As[rr][jj] = val;
+#pragma unroll
+        for (int e8 = 0; e8 < kPer; ++e8) {
+            const int e = threadIdx.x + 256 * e8;
+            As[e / kMmK][e % kMmK] = pre[e8];
         }
         __syncthreads();
+        if (j0 + kMmK < Wq) load_step(j0 + kMmK);
 #pragma unroll 4
         for (int kk = 0; kk < kMmK; kk += 2) {
             const float a = As[32 * wr + (lane & 31)][kk + (lane >> 5)];
@@ -195,7 +220,7 @@ __global__ __launch_bounds__(256) void fdk_filter_mfma_kernel(const float *__res
             if (i >= Wp) continue;
             const int u = 2 * i + p;
             const float acc = h == 0 ? acc0[e] : acc1[e];
-            const float qv = (acc + 0.25f * weighted_input(images, pw, vw, view, v, r, u, W)) * out_scale;
+            const float qv = fmaf(0.25f, xp[r * Wp + i], acc) * out_scale;
             row_x[u + 2].x = qv;
             row_y[u + 2].y = qv;
         }
@@ -303,7 +328,8 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
 }
 
 hipError_t launch_fdk(const float *images, const ViewGeom *nominal, const ViewGeom *moved, int n_views, int W,
-                      int H, FdkVolume vol, FdkView *views, float *pw, float2 *Qi, float *out, hipStream_t s) {
+                      int H, FdkVolume vol, FdkView *views, float *pw, float *xw, float2 *Qi, float *out,
+                      hipStream_t s) {
     hipLaunchKernelGGL(fdk_view_kernel, dim3((n_views + 255) / 256), dim3(256), 0, s, nominal, moved, n_views,
                        views);
     hipError_t e = hipGetLastError();
@@ -316,12 +342,17 @@ hipError_t launch_fdk(const float *images, const ViewGeom *nominal, const ViewGe
     hipLaunchKernelGGL(fdk_border_kernel, dim3((unsigned)((n_border + 255) / 256)), dim3(256), 0, s, n_views, W, H,
                        Qi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    float *x_even = xw, *x_odd = xw + (int64_t)n_views * H * ((W + 1) / 2);
+    hipLaunchKernelGGL(fdk_weight_kernel, dim3((unsigned)((int64_t)n_views * H), (W + 255) / 256), dim3(256), 0, s,
+                       images,
+                       (const FdkView *)views, (const float *)pw, W, H, x_even, x_odd);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int row_tiles = (int)(((int64_t)n_views * H + kMmRows - 1) / kMmRows);
     const int col_tiles = ((W + 1) / 2 + kMmCols - 1) / kMmCols;
     const int total = 2 * row_tiles * col_tiles;
     hipLaunchKernelGGL(fdk_filter_mfma_kernel, dim3((unsigned)(8 * ((total + 7) / 8))), dim3(256),
-                       sizeof(float) * W, s, images, (const FdkView *)views, (const float *)pw, n_views, W, H,
-                       row_tiles, col_tiles, Qi);
+                       sizeof(float) * W, s, (const float *)x_even, (const float *)x_odd, (const FdkView *)views,
+                       n_views, W, H, row_tiles, col_tiles, Qi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int tiles_x = (vol.nx + kBpTile - 1) / kBpTile, tiles_y = (vol.ny + kBpTile - 1) / kBpTile;
     const int n_tiles = tiles_x * tiles_y * ((vol.nz + kBpSlab - 1) / kBpSlab);

@@ -25,8 +25,10 @@ struct FdkVolume {
     float voxel_mm;
 };
 
-// pw: [n_views][W] scratch for the Parker weights; Qi: the filtered views.
+// pw: [n_views][W] scratch for the Parker weights; xw: [n_views H][W] scratch
+// for the weighted rows (split by column parity); Qi: the filtered views.
 hipError_t launch_fdk(const float *images, const ViewGeom *nominal, const ViewGeom *moved, int n_views, int W,
-                      int H, FdkVolume vol, FdkView *views, float *pw, float2 *Qi, float *out, hipStream_t s);
+                      int H, FdkVolume vol, FdkView *views, float *pw, float *xw, float2 *Qi, float *out,
+                      hipStream_t s);
 
 }  // namespace ecc
