@@ -41,7 +41,7 @@ __device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const T
     const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
     const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
     const float Bv = fmaf(c.fa, r1 - r0, r0);
-    const float w = fmaf(c.tf * c.tf, inv_f2, 1.0f);
+    const float w = fmaf(c.tf, c.tf * inv_f2, 1.0f);
     const float dB_da = (r1 - r0) * ec.inv_dalpha;
     const float dB_dt = fmaf(c.fa, (tp.s11 - tp.s10) - (tp.s01 - tp.s00), tp.s01 - tp.s00) * ec.inv_dt;
     // S = sgn * scale * w(t) * B(alpha, t) with (alpha, t) of the folded line

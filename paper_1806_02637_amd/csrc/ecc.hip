@@ -194,6 +194,9 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
                                                       float *__restrict__ out_pair, double *__restrict__ partials,
                                                       int n_tiles) {
+    // the column offset joins an FMA with two other scalar operands: keep it
+    // in a vector register for the whole kernel rather than copy it per plane
+    asm volatile("" : "+v"(ec.t0_tau));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int hyp_groups = (ec.B + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -214,7 +217,8 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     double wave_acc = 0.0;
     for (int q = 0; q < kPairsPerWave; ++q) {
         const PairConst<G> pc = UNIFORM ? uniform(slots[wave][q]) : slots[wave][q];
-        const int a = pc.va, b = pc.vb;
+        // view ids (and so the two sinogram bases) in scalar registers
+        const int a = uniform(pc.va), b = uniform(pc.vb);
         if (a < 0) continue;
         const int64_t p = pair_index(a, b, ec.n_views);
         const Tap *sa = base + (int64_t)a * ec.view_elems;

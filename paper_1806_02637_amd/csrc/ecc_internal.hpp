@@ -13,16 +13,18 @@ namespace ecc {
 // Resident sinogram layout.
 //
 // Row-interleaved: element (view, m, j) holds the pair (S[m][k], S[m+1][k])
-// with k = j - 1, for m = 0..n_alpha-1 and j = 0..n_t+1.  Columns j = 0 and
-// j = n_t + 1 are zero (t beyond the grid reads as 0).  Row m + 1 = n_alpha is
-// the pad row S(pi, t_k) = -S(0, t_{n_t-1-k}).  One 2-element load at
-// (m, k + 1) therefore returns all four bilinear taps of cell (m, k).
+// with k = j - 1, for m = 0..n_alpha and j = 0..n_t+1.  Columns j = 0 and
+// j = n_t + 1 are zero (t beyond the grid reads as 0).  Rows n_alpha and
+// n_alpha + 1 continue the sinogram past pi by its odd symmetry,
+// S(alpha + pi, t_k) = -S(alpha, t_{n_t-1-k}): row n_alpha is the pad row at
+// alpha = pi, row n_alpha + 1 the one a step beyond it.  One 2-element load
+// at (m, k + 1) therefore returns all four bilinear taps of cell (m, k).
 // FP32 storage: 8-byte elements; BF16 / FP16: 4-byte elements.
 // ---------------------------------------------------------------------------
 struct SinoLayout {
     int32_t n_views, n_alpha, n_t;
     int32_t row_elems;      // n_t + 2
-    int64_t view_elems;     // n_alpha * row_elems
+    int64_t view_elems;     // (n_alpha + 1) * row_elems
     int32_t dtype;          // ECC_F32 / ECC_BF16 / ECC_F16
     int32_t elem_bytes;     // 8 or 4
 };
@@ -33,7 +35,7 @@ inline SinoLayout make_layout(int n_views, int n_alpha, int n_t, int dtype) {
     L.n_alpha = n_alpha;
     L.n_t = n_t;
     L.row_elems = n_t + 2;
-    L.view_elems = (int64_t)n_alpha * L.row_elems;
+    L.view_elems = (int64_t)(n_alpha + 1) * L.row_elems;
     L.dtype = dtype;
     L.elem_bytes = dtype == 0 ? 8 : 4;
     return L;
@@ -63,10 +65,11 @@ struct EvalConsts {
     double R_mm;
     float inv_c;       // 1/c, 0 for c = inf
     float half_w, half_h;
-    // t0 = t_max + dt: (t + t0) / dt is the stored column coordinate of t
-    float t0, inv_dt, inv_dalpha;
+    // t / dt + t0_tau, t0_tau = (t_max + dt) / dt, is the stored column
+    // coordinate of t
+    float t0_tau, inv_dt, inv_dalpha;
     int32_t kappa_detector;  // 1: planes sample the arc both detectors see (else the object sphere's)
-    double t0_d, inv_dt_d, inv_dalpha_d;
+    double t0_tau_d, inv_dt_d, inv_dalpha_d;
 };
 
 // Pair index <-> (a, b), a < b, row-major triangle.

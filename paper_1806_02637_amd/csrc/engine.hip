@@ -191,10 +191,10 @@ EvalConsts make_consts(const Scan *s, int B, const ecc_eval_params *prm) {
     const double t_max = 0.5 * sqrt((double)s->W * s->W + (double)s->H * s->H);
     const double dt = 2.0 * t_max / (s->layout.n_t - 1);
     const double dalpha = M_PI / s->layout.n_alpha;
-    ec.t0_d = t_max + dt;
+    ec.t0_tau_d = (t_max + dt) / dt;
     ec.inv_dt_d = 1.0 / dt;
     ec.inv_dalpha_d = 1.0 / dalpha;
-    ec.t0 = (float)(t_max + dt);
+    ec.t0_tau = (float)((t_max + dt) / dt);
     ec.inv_dt = (float)(1.0 / dt);
     ec.inv_dalpha = (float)(1.0 / dalpha);
     return ec;
@@ -372,7 +372,7 @@ static ecc_status install_sinograms(ecc_ctx *ctx, Scan *s, int32_t n_alpha, int3
 ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, double ds_px,
                                     int32_t dtype, void *stream) {
     if (!ctx) return fail(ECC_E_ARG, "null context");
-    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 28))
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)(n_alpha + 1) * (n_t + 2) >= (1ll << 28))
         return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
     if (!(ds_px > 0.0) || ds_px > 1.0) return fail(ECC_E_ARG, "ds_px must be in (0, 1]");
     if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
@@ -387,7 +387,7 @@ ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alp
 ecc_status ecc_scan_set_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t, const float *sino,
                                   int32_t sino_on_device, int32_t dtype) {
     if (!ctx || !sino) return fail(ECC_E_ARG, "null argument");
-    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)n_alpha * (n_t + 2) >= (1ll << 28))
+    if (n_alpha < 2 || n_alpha > 65536 || n_t < 3 || n_t > 65536 || (int64_t)(n_alpha + 1) * (n_t + 2) >= (1ll << 28))
         return fail(ECC_E_ARG, "sinogram grid %d x %d out of range", n_alpha, n_t);
     if (dtype < ECC_F32 || dtype > ECC_F16) return fail(ECC_E_ARG, "unknown dtype %d", dtype);
     DeviceGuard g(ctx->device);

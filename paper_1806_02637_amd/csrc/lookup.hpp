@@ -126,9 +126,10 @@ __device__ __forceinline__ float g_angle(float ax, float ay, float rinv, bool xn
     const bool swap = ay > ax;
     const float s = (swap ? ax : ay) * rinv;
     const float s2 = s * s;
-    float p = kAsin[7];
+    constexpr int n = sizeof(kAsin) / sizeof(kAsin[0]);
+    float p = kAsin[n - 1];
 #pragma unroll
-    for (int i = 6; i >= 0; --i) p = fmaf(p, s2, kAsin[i]);
+    for (int i = n - 2; i >= 0; --i) p = fmaf(p, s2, kAsin[i]);
     const float off = swap ? 1.57079632679489662f : (xneg ? 3.14159265358979324f : 0.0f);
     return fmaf(swap != xneg ? -s : s, p, off);
 }
@@ -157,14 +158,32 @@ __device__ __forceinline__ double g_rsqrt(double x) {
 __device__ __forceinline__ float g_clamp(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 __device__ __forceinline__ double g_clamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 
+// Grid cell of a coordinate x: returns the fraction x - floor(x) and sets i =
+// floor(x) clamped to [0, hi].  Lanes whose line hits a detector have x in
+// [0, hi + 1), where the two agree; on the others the clamp only keeps the
+// address in range (the FP32 convert-with-floor gives 0 for NaN and
+// saturates infinities).
+__device__ __forceinline__ float cell_split(float x, float hi, int &i) {
+    // clamp (a NaN input yields 0 or NaN), then floor and convert in one
+    // instruction, which turns NaN into 0
+    const float xc = __builtin_amdgcn_fmed3f(x, 0.0f, hi);
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(xc));
+    return __builtin_amdgcn_fractf(x);
+}
+__device__ __forceinline__ float cell_split(double x, double hi, int &i) {
+    const double fl = floor(x);
+    i = (int)g_clamp(fl, 0.0, hi);
+    return (float)(x - fl);
+}
+
 template <class G> struct GConst;
 template <> struct GConst<float> {
-    static __device__ __forceinline__ float t0(const EvalConsts &e) { return e.t0; }
+    static __device__ __forceinline__ float t0_tau(const EvalConsts &e) { return e.t0_tau; }
     static __device__ __forceinline__ float inv_dt(const EvalConsts &e) { return e.inv_dt; }
     static __device__ __forceinline__ float inv_dalpha(const EvalConsts &e) { return e.inv_dalpha; }
 };
 template <> struct GConst<double> {
-    static __device__ __forceinline__ double t0(const EvalConsts &e) { return e.t0_d; }
+    static __device__ __forceinline__ double t0_tau(const EvalConsts &e) { return e.t0_tau_d; }
     static __device__ __forceinline__ double inv_dt(const EvalConsts &e) { return e.inv_dt_d; }
     static __device__ __forceinline__ double inv_dalpha(const EvalConsts &e) { return e.inv_dalpha_d; }
 };
@@ -182,7 +201,7 @@ struct LineCoord {
     G l1, l2, l3, rinv;  // folded line, 1/|(l1, l2)|
     G r2, edge;          // |(l1, l2)|^2, (W/2)|l1| + (H/2)|l2|
     float fa, ft, tf;    // bilinear fractions, folded t (FP32)
-    int m, j;            // cell: row m, stored column j = k + 1 (clamped for memory safety)
+    int m, j;            // cell: row m <= n_alpha, stored column j = k + 1 (clamped for memory safety)
     bool hit, fold;      // fold: the line was negated (sign -1 on S)
 };
 
@@ -210,16 +229,14 @@ __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, con
     // |t| <= (W/2)|cos a| + (H/2)|sin a|  <=>  |l3| <= (W/2)|l1| + (H/2)|l2|
     c.edge = (G)ec.half_w * fabs(l1) + (G)ec.half_h * fabs(l2);
     c.hit = (r2 > (G)0) & (fabs(l3) <= c.edge);
-    const G aa = alpha * GConst<G>::inv_dalpha(ec);
-    const G mf = g_clamp(floor(aa), (G)0, (G)(ec.n_alpha - 1));
-    // stored column coordinate: column j holds t_{j-1}, so j = tau + 1 with
-    // tau = (t + t_max) / dt; t0 = t_max + dt
-    const G tau = (t + GConst<G>::t0(ec)) * GConst<G>::inv_dt(ec);
-    const G jf = g_clamp(floor(tau), (G)0, (G)ec.n_t);
-    c.fa = (float)(aa - mf);
-    c.ft = (float)(tau - jf);
-    c.m = (int)mf;
-    c.j = (int)jf;
+    // alpha <= pi (rounded up by at most an ulp) puts row m <= n_alpha: the
+    // stored cell rows run to n_alpha, whose upper row continues the
+    // sinogram past pi
+    c.fa = cell_split(alpha * GConst<G>::inv_dalpha(ec), (G)ec.n_alpha, c.m);
+    // stored column coordinate: column j holds t_{j-1}, so j = tau with
+    // tau = (t + t_max + dt) / dt = t / dt + t0_tau
+    const G tau = fma(t, GConst<G>::inv_dt(ec), GConst<G>::t0_tau(ec));
+    c.ft = cell_split(tau, (G)ec.n_t, c.j);
     c.tf = (float)t;
     return c;
 }
@@ -255,7 +272,7 @@ __device__ __forceinline__ float bilerp(const Taps &tp, float fa, float ft) {
 // Grangeat weight 1 + t^2 / f^2, times the storage scale of scaled types.
 template <class Tap>
 __device__ __forceinline__ float grangeat_weight(float t, float inv_f2, float scale) {
-    const float w = fmaf(t * t, inv_f2, 1.0f);
+    const float w = fmaf(t, t * inv_f2, 1.0f);
     return Tap::kScaled ? w * scale : w;
 }
 

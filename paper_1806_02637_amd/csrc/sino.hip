@@ -215,17 +215,19 @@ hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *in
 }
 
 // ---------------------------------------------------------------------------
-// Stored value at (m, k), m = 0..n_alpha (row n_alpha = alpha = pi), from
-// either the line integrals G (central difference) or an external sinogram.
+// Stored value at (m, k), m = 0..n_alpha + 1, from either the line integrals
+// G (central difference) or an external sinogram [n_alpha + 1][n_t].  Rows
+// past pi follow from the odd symmetry S(alpha + pi, t) = -S(alpha, -t); an
+// external sinogram supplies its own row n_alpha (alpha = pi).
 __device__ __forceinline__ double drho_at(const double *G, const float *ext, int v, int m, int k, int n_alpha,
                                           int n_t, double inv_2dt) {
-    if (ext) return (double)ext[((int64_t)v * (n_alpha + 1) + m) * n_t + k];
     double sign = 1.0;
-    if (m == n_alpha) {
-        m = 0;
+    if (m >= n_alpha && !(ext && m == n_alpha)) {
+        m -= n_alpha;
         k = n_t - 1 - k;
         sign = -1.0;
     }
+    if (ext) return sign * (double)ext[((int64_t)v * (n_alpha + 1) + m) * n_t + k];
     const double *row = G + ((int64_t)v * n_alpha + m) * n_t;
     const double hi = k + 1 < n_t ? row[k + 1] : 0.0;
     const double lo = k - 1 >= 0 ? row[k - 1] : 0.0;
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(256) void sino_store_kernel(const double *G, const 
         lo = (float)drho_at(G, ext, v, m, k, n_alpha, n_t, inv_2dt);
         hi = (float)drho_at(G, ext, v, m + 1, k, n_alpha, n_t, inv_2dt);
     }
-    const int64_t e = ((int64_t)v * n_alpha + m) * row_elems + j;
+    const int64_t e = ((int64_t)v * (n_alpha + 1) + m) * row_elems + j;
     if (dtype == 0) {
         float2 *out = (float2 *)sino;
         out[e] = make_float2(lo, hi);
@@ -318,7 +320,7 @@ hipError_t launch_sino_store(const double *G, const float *ext, int n_views, int
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    dim3 g2((n_t + 2 + 255) / 256, n_alpha, n_views);
+    dim3 g2((n_t + 2 + 255) / 256, n_alpha + 1, n_views);
     hipLaunchKernelGGL(sino_store_kernel, g2, dim3(256), 0, s, G, ext, n_alpha, n_t, inv_2dt, dtype, sino,
                        view_scale, view_absmax);
     return hipGetLastError();
