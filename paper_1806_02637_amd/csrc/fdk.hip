@@ -255,6 +255,16 @@ constexpr int kBpTile = 16;   // voxel columns per workgroup side
 constexpr int kBpSlab = 16;   // slices per thread
 constexpr int kBpStage = 128;  // views staged in LDS at a time
 
+// Cell of a padded-view coordinate x: returns the fraction x - floor(x) and
+// sets i = floor(x) clamped to [0, hi] (one floor-and-convert instruction on
+// the clamped value).  Coordinates are finite: the voxel's projection with
+// the reciprocal depth set to 0 behind the source.
+__device__ __forceinline__ float bp_cell(float x, float hi, int &i) {
+    const float xc = __builtin_amdgcn_fmed3f(x, 0.0f, hi);
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(xc));
+    return __builtin_amdgcn_fractf(x);
+}
+
 // Workgroups are numbered so that each XCD (8 per chip, blocks dealt to them
 // round-robin) takes one contiguous range of tiles, x fastest then y then z:
 // a z-slab of the volume, whose footprint in every view is a band of rows
@@ -280,10 +290,21 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
     const float z0 = ((float)iz0 - 0.5f * (float)(vol.nz - 1)) * s;
     const uint32_t WP = (uint32_t)W + 4;
     const int64_t view_bytes = (int64_t)(H + 3) * WP * sizeof(float2);
-    const float u_hi = (float)W, v_hi = (float)H;
+    // cell coordinates in the padded view (detector column u at u + 2, row v
+    // at pair row v + 2): cells past the detector are clamped into the
+    // two-wide zero border, where all four taps read zero
+    const float u_hi = (float)(W + 2), v_hi = (float)(H + 2);
     float acc[kBpSlab];
 #pragma unroll
     for (int k = 0; k < kBpSlab; ++k) acc[k] = 0.0f;
+    // one bilinear read of cell (iu, iv) at fractions (fu, fv)
+    auto read = [&](const char *q, int iu, int iv, float fu, float fv) {
+        const uint32_t e = __umul24((uint32_t)iv, WP) + (uint32_t)iu;
+        const fdk_f32x4_a8 t = *(const fdk_f32x4_a8 *)(q + e * (uint32_t)sizeof(float2));
+        const float top = fmaf(fu, t.z - t.x, t.x);
+        const float bot = fmaf(fu, t.w - t.y, t.y);
+        return fmaf(fv, bot - top, top);
+    };
     for (int v0 = 0; v0 < n_views; v0 += kBpStage) {
         const int nv = min(kBpStage, n_views - v0);
         __syncthreads();
@@ -294,28 +315,40 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
             const float a0 = fmaf(w.P[0], x, fmaf(w.P[1], y, fmaf(w.P[2], z0, w.P[3])));
             const float b0 = fmaf(w.P[4], x, fmaf(w.P[5], y, fmaf(w.P[6], z0, w.P[7])));
             const float c0 = fmaf(w.P[8], x, fmaf(w.P[9], y, fmaf(w.P[10], z0, w.P[11])));
-            const float da = w.P[2] * s, db = w.P[6] * s, dc = w.P[10] * s;
+            const float db = w.P[6] * s;
+            const float u0p = w.u0 + 2.0f, v0p = w.v0 + 2.0f;
             const char *q = (const char *)Qi + (int64_t)(v0 + j) * view_bytes;
+            if (w.P[2] == 0.0f && w.P[10] == 0.0f) {
+                // the view's column and depth do not change along z (a
+                // circular orbit about z, moved by translations and
+                // rotations about z): column, weight and reciprocal once per
+                // voxel column, only the row moves.  The values equal the
+                // general branch's, whose z terms vanish exactly.
+                const float rc = c0 > 0.0f ? __builtin_amdgcn_rcpf(c0) : 0.0f;
+                const float wgt = rc * rc;
+                int iu;
+                const float fu = bp_cell(fmaf(a0, rc, u0p), u_hi, iu);
 #pragma unroll
-            for (int k = 0; k < kBpSlab; ++k) {
-                const float a = fmaf((float)k, da, a0);
-                const float b = fmaf((float)k, db, b0);
-                const float c = fmaf((float)k, dc, c0);
-                // a point behind the source counts zero (rc = 0 also keeps
-                // its coordinates finite)
-                const float rc = c > 0.0f ? __builtin_amdgcn_rcpf(c) : 0.0f;
-                const float u = fmaf(a, rc, w.u0), vv = fmaf(b, rc, w.v0);
-                // cells off the detector are clamped into the two-wide zero
-                // border: any point outside reads four zeros
-                const float uf = __builtin_amdgcn_fmed3f(floorf(u), -2.0f, u_hi);
-                const float vf = __builtin_amdgcn_fmed3f(floorf(vv), -2.0f, v_hi);
-                const float fu = u - uf, fv = vv - vf;
-                const uint32_t e = __umul24((uint32_t)((int)vf + 2), WP) + (uint32_t)((int)uf + 2);
-                const fdk_f32x4_a8 t = *(const fdk_f32x4_a8 *)(q + e * (uint32_t)sizeof(float2));
-                const float top = fmaf(fu, t.z - t.x, t.x);
-                const float bot = fmaf(fu, t.w - t.y, t.y);
-                const float val = fmaf(fv, bot - top, top);
-                acc[k] = fmaf(rc * rc, val, acc[k]);
+                for (int k = 0; k < kBpSlab; ++k) {
+                    int iv;
+                    const float fv = bp_cell(fmaf(fmaf((float)k, db, b0), rc, v0p), v_hi, iv);
+                    acc[k] = fmaf(wgt, read(q, iu, iv, fu, fv), acc[k]);
+                }
+            } else {
+                const float da = w.P[2] * s, dc = w.P[10] * s;
+#pragma unroll
+                for (int k = 0; k < kBpSlab; ++k) {
+                    const float a = fmaf((float)k, da, a0);
+                    const float b = fmaf((float)k, db, b0);
+                    const float c = fmaf((float)k, dc, c0);
+                    // a point behind the source counts zero (rc = 0 also
+                    // keeps its coordinates finite)
+                    const float rc = c > 0.0f ? __builtin_amdgcn_rcpf(c) : 0.0f;
+                    int iu, iv;
+                    const float fu = bp_cell(fmaf(a, rc, u0p), u_hi, iu);
+                    const float fv = bp_cell(fmaf(b, rc, v0p), v_hi, iv);
+                    acc[k] = fmaf(rc * rc, read(q, iu, iv, fu, fv), acc[k]);
+                }
             }
         }
     }
