@@ -26,6 +26,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ecc_internal.hpp"
 #include "fdk.hpp"
 
@@ -253,7 +255,15 @@ __global__ __launch_bounds__(256) void fdk_border_kernel(int n_views, int W, int
 
 constexpr int kBpTile = 16;   // voxel columns per workgroup side
 constexpr int kBpSlab = 16;   // slices per thread
-constexpr int kBpStage = 128;  // views staged in LDS at a time
+// LDS window of one view: up to kBpRows pair rows x kBpCols pair elements,
+// wave w staging rows w, w + 4, ... (one element per lane).  Rows are
+// kBpPitch elements apart, so that the rows of a gather start on different
+// LDS banks.
+constexpr int kBpCols = 64;
+constexpr int kBpRows = 56;
+constexpr int kBpPitch = 66;
+constexpr int kBpPer = kBpRows / 4;  // rows each wave stages per view
+constexpr int kBpWinChunk = 256;     // views whose windows are computed together
 
 // Cell of a padded-view coordinate x: returns the fraction x - floor(x) and
 // sets i = floor(x) clamped to [0, hi] (one floor-and-convert instruction on
@@ -265,31 +275,78 @@ __device__ __forceinline__ float bp_cell(float x, float hi, int &i) {
     return __builtin_amdgcn_fractf(x);
 }
 
+// The part of one padded filtered view that a workgroup's 16 x 16 x 16 voxel
+// box reads: element rows [v_lo, v_lo + rows) x columns [u_lo, u_lo + cols).
+// The box lies in front of the source, so its projection is the convex hull
+// of its 8 corner voxels' projections.  One cell of margin on each side
+// covers the rounding of the per-voxel coordinates; the cell indices are
+// clamped as the per-voxel ones, and the window takes one more column for a
+// cell's second column (also when the whole box projects past the
+// detector's edge).  cols = 0 when a corner is not in front of the source or
+// the window exceeds the LDS tile (the view is then read directly).
+__device__ __forceinline__ short4 bp_window(const FdkView &w, float xb, float yb, float zb, float ext, int W,
+                                            int H) {
+    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, cmin = INFINITY;
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
+        const float X = (corner & 1) ? xb + ext : xb, Y = (corner & 2) ? yb + ext : yb;
+        const float Z = (corner & 4) ? zb + ext : zb;
+        const float a = fmaf(w.P[0], X, fmaf(w.P[1], Y, fmaf(w.P[2], Z, w.P[3])));
+        const float b = fmaf(w.P[4], X, fmaf(w.P[5], Y, fmaf(w.P[6], Z, w.P[7])));
+        const float c = fmaf(w.P[8], X, fmaf(w.P[9], Y, fmaf(w.P[10], Z, w.P[11])));
+        const float rc = c > 0.0f ? __builtin_amdgcn_rcpf(c) : 0.0f;
+        const float u = fmaf(a, rc, w.u0 + 2.0f), v = fmaf(b, rc, w.v0 + 2.0f);
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
+        vmin = fminf(vmin, v);
+        vmax = fmaxf(vmax, v);
+        cmin = fminf(cmin, c);
+    }
+    const float ulo = __builtin_amdgcn_fmed3f(floorf(umin) - 1.0f, 0.0f, (float)(W + 2));
+    const float uhi = __builtin_amdgcn_fmed3f(floorf(umax) + 1.0f, 0.0f, (float)(W + 2)) + 1.0f;
+    const float vlo = __builtin_amdgcn_fmed3f(floorf(vmin) - 1.0f, 0.0f, (float)(H + 2));
+    const float vhi = __builtin_amdgcn_fmed3f(floorf(vmax) + 1.0f, 0.0f, (float)(H + 2));
+    const bool fits = cmin > 0.0f && uhi - ulo < (float)kBpCols && vhi - vlo < (float)kBpRows;
+    if (!fits) return make_short4(0, 0, 0, 0);
+    return make_short4((short)ulo, (short)vlo, (short)(vhi - vlo + 1.0f), (short)(uhi - ulo + 1.0f));
+}
+
 // Workgroups are numbered so that each XCD (8 per chip, blocks dealt to them
 // round-robin) takes one contiguous range of tiles, x fastest then y then z:
-// a z-slab of the volume, whose footprint in every view is a band of rows
-// that fits the XCD's L2.
+// a z-slab of the volume, whose footprint in every view is a band of rows.
+//
+// Each view's window is loaded once per workgroup into LDS (loads for view
+// j + 1 in flight in registers while view j is computed) and every voxel
+// reads its cells there: a window element serves about five updates, which
+// otherwise each fetch a cache line of their own from L2.  Views whose
+// window does not fit read the filtered view directly.
 __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__restrict__ Qi,
                                                               const FdkView *__restrict__ views, int n_views,
                                                               int W, int H, FdkVolume vol, int tiles_x, int tiles_y,
                                                               int n_tiles, float *__restrict__ out) {
-    __shared__ FdkView sv[kBpStage];
+    __shared__ float2 win_lds[kBpRows * kBpPitch];
+    __shared__ short4 wins[2][kBpWinChunk];  // windows of two chunks of views
     const int per = (n_tiles + 7) / 8;
     const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (tile >= n_tiles) return;  // no barrier has been reached yet
     const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
     // each wave takes an 8 x 8 quarter of the 16 x 16 tile: its 64 voxel
-    // columns project onto a compact detector patch (few cache lines per gather)
+    // columns project onto a compact detector patch
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ix = tx * kBpTile + (wave & 1) * 8 + (lane & 7);
     const int iy = ty * kBpTile + (wave >> 1) * 8 + (lane >> 3);
     const int iz0 = tz * kBpSlab;
     const float s = vol.voxel_mm;
-    const float x = ((float)ix - 0.5f * (float)(vol.nx - 1)) * s;
-    const float y = ((float)iy - 0.5f * (float)(vol.ny - 1)) * s;
-    const float z0 = ((float)iz0 - 0.5f * (float)(vol.nz - 1)) * s;
+    const float hx = 0.5f * (float)(vol.nx - 1), hy = 0.5f * (float)(vol.ny - 1), hz = 0.5f * (float)(vol.nz - 1);
+    const float x = ((float)ix - hx) * s;
+    const float y = ((float)iy - hy) * s;
+    const float z0 = ((float)iz0 - hz) * s;
+    // the workgroup's voxel box (centres of its corner voxels)
+    const float xb = ((float)(tx * kBpTile) - hx) * s, yb = ((float)(ty * kBpTile) - hy) * s;
+    const float ext = (float)(kBpTile - 1) * s;
+    static_assert(kBpTile == kBpSlab, "the window's box is a cube");
     const uint32_t WP = (uint32_t)W + 4;
-    const int64_t view_bytes = (int64_t)(H + 3) * WP * sizeof(float2);
+    const int64_t view_elems = (int64_t)(H + 3) * WP;
     // cell coordinates in the padded view (detector column u at u + 2, row v
     // at pair row v + 2): cells past the detector are clamped into the
     // two-wide zero border, where all four taps read zero
@@ -297,60 +354,115 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
     float acc[kBpSlab];
 #pragma unroll
     for (int k = 0; k < kBpSlab; ++k) acc[k] = 0.0f;
-    // one bilinear read of cell (iu, iv) at fractions (fu, fv)
-    auto read = [&](const char *q, int iu, int iv, float fu, float fv) {
-        const uint32_t e = __umul24((uint32_t)iv, WP) + (uint32_t)iu;
-        const fdk_f32x4_a8 t = *(const fdk_f32x4_a8 *)(q + e * (uint32_t)sizeof(float2));
+    // staging: wave w moves window rows w + 4 i, lane l their column l
+    const int sw = __builtin_amdgcn_readfirstlane(wave);
+    float2 pre[kBpPer];
+    auto prefetch = [&](const short4 &wn, int view) {
+        const float2 *src = Qi + view * view_elems + (int64_t)(wn.y + sw) * WP + wn.x;
+        if (lane < wn.w) {
+#pragma unroll
+            for (int i = 0; i < kBpPer; ++i)
+                if (sw + 4 * i < wn.z) pre[i] = src[(uint32_t)(4 * i) * WP + lane];
+        }
+    };
+    auto stage = [&](const short4 &wn) {
+        if (lane < wn.w) {
+#pragma unroll
+            for (int i = 0; i < kBpPer; ++i)
+                if (sw + 4 * i < wn.z) win_lds[(sw + 4 * i) * kBpPitch + lane] = pre[i];
+        }
+    };
+    // windows of views [c kBpWinChunk, (c + 1) kBpWinChunk), one per thread
+    auto chunk_windows = [&](int c) {
+        const int v = c * kBpWinChunk + (int)threadIdx.x;
+        if (v < n_views) wins[c & 1][threadIdx.x] = bp_window(views[v], xb, yb, z0, ext, W, H);
+    };
+    auto window_of = [&](int v) {
+        const short4 r = wins[(v / kBpWinChunk) & 1][v % kBpWinChunk];
+        return make_short4((short)__builtin_amdgcn_readfirstlane(r.x), (short)__builtin_amdgcn_readfirstlane(r.y),
+                           (short)__builtin_amdgcn_readfirstlane(r.z), (short)__builtin_amdgcn_readfirstlane(r.w));
+    };
+    // bilinear value of cell (iu, iv) at fractions (fu, fv), from the window
+    // (FROM_LDS) or from the view
+    auto bilerp = [](const fdk_f32x4_a8 &t, float fu, float fv) {
         const float top = fmaf(fu, t.z - t.x, t.x);
         const float bot = fmaf(fu, t.w - t.y, t.y);
         return fmaf(fv, bot - top, top);
     };
-    for (int v0 = 0; v0 < n_views; v0 += kBpStage) {
-        const int nv = min(kBpStage, n_views - v0);
-        __syncthreads();
-        for (int i = threadIdx.x; i < nv; i += blockDim.x) sv[i] = views[v0 + i];
-        __syncthreads();
-        for (int j = 0; j < nv; ++j) {
-            const FdkView &w = sv[j];
-            const float a0 = fmaf(w.P[0], x, fmaf(w.P[1], y, fmaf(w.P[2], z0, w.P[3])));
-            const float b0 = fmaf(w.P[4], x, fmaf(w.P[5], y, fmaf(w.P[6], z0, w.P[7])));
-            const float c0 = fmaf(w.P[8], x, fmaf(w.P[9], y, fmaf(w.P[10], z0, w.P[11])));
-            const float db = w.P[6] * s;
-            const float u0p = w.u0 + 2.0f, v0p = w.v0 + 2.0f;
-            const char *q = (const char *)Qi + (int64_t)(v0 + j) * view_bytes;
-            if (w.P[2] == 0.0f && w.P[10] == 0.0f) {
-                // the view's column and depth do not change along z (a
-                // circular orbit about z, moved by translations and
-                // rotations about z): column, weight and reciprocal once per
-                // voxel column, only the row moves.  The values equal the
-                // general branch's, whose z terms vanish exactly.
-                const float rc = c0 > 0.0f ? __builtin_amdgcn_rcpf(c0) : 0.0f;
-                const float wgt = rc * rc;
-                int iu;
-                const float fu = bp_cell(fmaf(a0, rc, u0p), u_hi, iu);
-#pragma unroll
-                for (int k = 0; k < kBpSlab; ++k) {
-                    int iv;
-                    const float fv = bp_cell(fmaf(fmaf((float)k, db, b0), rc, v0p), v_hi, iv);
-                    acc[k] = fmaf(wgt, read(q, iu, iv, fu, fv), acc[k]);
-                }
+    // the updates of one view; FROM_LDS is the same for the whole workgroup
+    auto view_updates = [&](const FdkView &w, const float2 *q, const short4 &wn, auto from_lds) {
+        constexpr bool FROM_LDS = decltype(from_lds)::value;
+        auto cell = [&](int iu, int iv, float fu, float fv) {
+            fdk_f32x4_a8 t;
+            if (FROM_LDS) {
+                t = *(const fdk_f32x4_a8 *)(win_lds + ((iv - wn.y) * kBpPitch + (iu - wn.x)));
             } else {
-                const float da = w.P[2] * s, dc = w.P[10] * s;
+                const uint32_t e = __umul24((uint32_t)iv, WP) + (uint32_t)iu;
+                t = *(const fdk_f32x4_a8 *)((const char *)q + e * (uint32_t)sizeof(float2));
+            }
+            return bilerp(t, fu, fv);
+        };
+        const float a0 = fmaf(w.P[0], x, fmaf(w.P[1], y, fmaf(w.P[2], z0, w.P[3])));
+        const float b0 = fmaf(w.P[4], x, fmaf(w.P[5], y, fmaf(w.P[6], z0, w.P[7])));
+        const float c0 = fmaf(w.P[8], x, fmaf(w.P[9], y, fmaf(w.P[10], z0, w.P[11])));
+        const float db = w.P[6] * s;
+        const float u0p = w.u0 + 2.0f, v0p = w.v0 + 2.0f;
+        if (w.P[2] == 0.0f && w.P[10] == 0.0f) {
+            // the view's column and depth do not change along z (a circular
+            // orbit about z, moved by translations and rotations about z):
+            // column, weight and reciprocal once per voxel column, only the
+            // row moves.  The values equal the general branch's, whose z
+            // terms vanish exactly.
+            const float rc = c0 > 0.0f ? __builtin_amdgcn_rcpf(c0) : 0.0f;
+            const float wgt = rc * rc;
+            int iu;
+            const float fu = bp_cell(fmaf(a0, rc, u0p), u_hi, iu);
 #pragma unroll
-                for (int k = 0; k < kBpSlab; ++k) {
-                    const float a = fmaf((float)k, da, a0);
-                    const float b = fmaf((float)k, db, b0);
-                    const float c = fmaf((float)k, dc, c0);
-                    // a point behind the source counts zero (rc = 0 also
-                    // keeps its coordinates finite)
-                    const float rc = c > 0.0f ? __builtin_amdgcn_rcpf(c) : 0.0f;
-                    int iu, iv;
-                    const float fu = bp_cell(fmaf(a, rc, u0p), u_hi, iu);
-                    const float fv = bp_cell(fmaf(b, rc, v0p), v_hi, iv);
-                    acc[k] = fmaf(rc * rc, read(q, iu, iv, fu, fv), acc[k]);
-                }
+            for (int k = 0; k < kBpSlab; ++k) {
+                int iv;
+                const float fv = bp_cell(fmaf(fmaf((float)k, db, b0), rc, v0p), v_hi, iv);
+                acc[k] = fmaf(wgt, cell(iu, iv, fu, fv), acc[k]);
+            }
+        } else {
+            const float da = w.P[2] * s, dc = w.P[10] * s;
+#pragma unroll
+            for (int k = 0; k < kBpSlab; ++k) {
+                const float a = fmaf((float)k, da, a0);
+                const float b = fmaf((float)k, db, b0);
+                const float c = fmaf((float)k, dc, c0);
+                // a point behind the source counts zero (rc = 0 also keeps
+                // its coordinates finite)
+                const float rc = c > 0.0f ? __builtin_amdgcn_rcpf(c) : 0.0f;
+                int iu, iv;
+                const float fu = bp_cell(fmaf(a, rc, u0p), u_hi, iu);
+                const float fv = bp_cell(fmaf(b, rc, v0p), v_hi, iv);
+                acc[k] = fmaf(rc * rc, cell(iu, iv, fu, fv), acc[k]);
             }
         }
+    };
+    chunk_windows(0);
+    __syncthreads();
+    short4 next = window_of(0);
+    if (next.w) prefetch(next, 0);
+    for (int j = 0; j < n_views; ++j) {
+        const FdkView &w = views[j];
+        const short4 cur = next;
+        // the next chunk's windows, written to the buffer whose last reads
+        // (views of the chunk before this one) ended two barriers ago; the
+        // barrier below orders them before their first read
+        if (j % kBpWinChunk == 0) chunk_windows(j / kBpWinChunk + 1);
+        __syncthreads();  // every wave is done with the previous window
+        if (cur.w) stage(cur);
+        __syncthreads();
+        if (j + 1 < n_views) {
+            next = window_of(j + 1);
+            if (next.w) prefetch(next, j + 1);
+        }
+        const float2 *q = Qi + j * view_elems;
+        if (cur.w)
+            view_updates(w, q, cur, std::true_type{});
+        else
+            view_updates(w, q, cur, std::false_type{});
     }
     if (ix >= vol.nx || iy >= vol.ny) return;
 #pragma unroll
