@@ -88,6 +88,32 @@ def test_fdk_ragged_shapes(eng):
     scan.free()
 
 
+def test_fdk_large_voxels_mixed_paths(eng):
+    """Voxels so large that the first workgroup's 16-voxel box spans more
+    detector columns than an LDS window holds in every view (read directly
+    from the filtered projections), while the boxes past the volume's edge,
+    clamped at the detector's border, fit in some views and not in others:
+    both paths, and the switch between them from view to view, static and
+    moved."""
+    import torch
+
+    _say("case: fdk 121 views 96x96, 20^3 at 6.5 mm (no view fits a window)")
+    g = inputs.ScanGeometry(121, 96, 96, 2.4)
+    P, intr, betas, arc = g.projection_matrices(), g.intrinsics(), g.orbit_angles(), math.radians(g.arc_deg)
+    ph = inputs.random_phantom(6, 6, contained_radius=0.9 * g.fov_radius())
+    theta = inputs.smooth_motion(9, g.n_views, peak=3.0, params=(1, 3, 5))
+    vol = ofdk.Volume(20, 20, 20, 6.5)
+    static = inputs.project(g, ph)
+    moved = inputs.project(g, ph, motion=theta)
+    scan = _scan(eng, g, static)
+    got = scan.fdk(torch.tensor(static, device="cuda"), (20, 20, 20, 6.5)).cpu().numpy()
+    _compare(got, ofdk.fdk(static, P, intr, betas, arc, g.sid_mm, vol), "static")
+    Pm = np.array([moved_projection([list(r) for r in P[i]], list(theta[i])) for i in range(g.n_views)])
+    got = scan.fdk(torch.tensor(moved, device="cuda"), (20, 20, 20, 6.5), theta=theta).cpu().numpy()
+    _compare(got, ofdk.fdk(moved, P, intr, betas, arc, g.sid_mm, vol, moved_P=Pm), "compensated")
+    scan.free()
+
+
 def test_fdk_full496_sampled(eng):
     """The 496-view 1240 x 960 scan into 512^3 voxels of 0.4 mm (the size the
     benchmark times): sampled voxels recomputed one by one by the oracle from
