@@ -32,29 +32,35 @@
 
 namespace ecc {
 
-// Reverse sweep through one view's lookup: accumulates dE/dH (6) and the
-// plane-angle derivative dE/dkappa_k given gS = dE/dS.
+// Reverse sweep through one view's lookup: accumulates dE/dH (6) given
+// gS = dE/dS, and the same terms weighted by u (the plane's position in its
+// range), from which the plane-angle sensitivities follow once per pair.
+// With the folded line l' (the fold sign cancels in dS/dl), r = |(l1', l2')|,
+// n = (l1', l2') / r, alpha = atan2(l2', l1') and t = -l3' / r:
+//   dalpha/dl' = (-n2, n1, 0) / r,   dt/dl' = -(t n1, t n2, 1) / r,
+// so with A = gS dS/dalpha / r and T = gS dS/dt / r:
+//   dE/dl' = (-(A n2 + T t n1), A n1 - T t n2, -T).
 template <class Tap, class G>
-__device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const Taps &tp, const EvalConsts &ec,
-                                               float inv_f2, float scale, float gS, const LineCoord<G> &c,
-                                               float gH[6], float &gk) {
-    const float r0 = fmaf(c.ft, tp.s01 - tp.s00, tp.s00);
-    const float r1 = fmaf(c.ft, tp.s11 - tp.s10, tp.s10);
+__device__ __forceinline__ void lookup_adjoint(G cs, G sn, const Taps &tp, const EvalConsts &ec, float inv_f2,
+                                               float scale, float gS, const LineCoord<G> &c, float u, float gH[6],
+                                               float gHu[6]) {
+    const float d0 = tp.s01 - tp.s00, d1 = tp.s11 - tp.s10;
+    const float r0 = fmaf(c.ft, d0, tp.s00);
+    const float r1 = fmaf(c.ft, d1, tp.s10);
     const float Bv = fmaf(c.fa, r1 - r0, r0);
-    const float w = fmaf(c.tf, c.tf * inv_f2, 1.0f);
-    const float dB_da = (r1 - r0) * ec.inv_dalpha;
-    const float dB_dt = fmaf(c.fa, (tp.s11 - tp.s10) - (tp.s01 - tp.s00), tp.s01 - tp.s00) * ec.inv_dt;
-    // S = sgn * scale * w(t) * B(alpha, t) with (alpha, t) of the folded line
-    // l' = sgn * l; the two factors sgn cancel in dS/dl, so with
-    // alpha = atan2(l2', l1') and t = -l3' / r:
-    const float dS_dalpha = scale * w * dB_da;
-    const float dS_dt = scale * (2.0f * c.tf * inv_f2 * Bv + w * dB_dt);
-    const float l1 = (float)c.l1, l2 = (float)c.l2, l3 = (float)c.l3;
+    const float x = c.tf * inv_f2;
+    const float w = fmaf(c.tf, x, 1.0f);
+    // S = sgn * scale * w(t) * B(alpha, t): dS/dalpha, dS/dt (without scale)
+    const float dS_dalpha = w * (r1 - r0) * ec.inv_dalpha;
+    const float dS_dt = fmaf(2.0f * x, Bv, w * ec.inv_dt * fmaf(c.fa, d1 - d0, d0));
     const float rinv = (float)c.rinv;
-    const float rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
-    const float gl1 = gS * (dS_dalpha * (-l2 * rinv2) + dS_dt * (l3 * l1 * rinv3));
-    const float gl2 = gS * (dS_dalpha * (l1 * rinv2) + dS_dt * (l3 * l2 * rinv3));
-    const float gl3 = gS * (dS_dt * (-rinv));
+    const float gr = Tap::kScaled ? gS * scale * rinv : gS * rinv;
+    const float A = gr * dS_dalpha, T = gr * dS_dt;
+    const float Tt = T * c.tf;
+    const float n1 = (float)c.l1 * rinv, n2 = (float)c.l2 * rinv;
+    const float gl1 = -fmaf(A, n2, Tt * n1);
+    const float gl2 = fmaf(A, n1, -(Tt * n2));
+    const float gl3 = -T;
     const float fc = (float)cs, fs = (float)sn;
     gH[0] = fmaf(gl1, fc, gH[0]);
     gH[1] = fmaf(gl2, fc, gH[1]);
@@ -62,9 +68,24 @@ __device__ __forceinline__ void lookup_adjoint(const G h[6], G cs, G sn, const T
     gH[3] = fmaf(gl1, fs, gH[3]);
     gH[4] = fmaf(gl2, fs, gH[4]);
     gH[5] = fmaf(gl3, fs, gH[5]);
-    // dl/dkappa = H (-sin, cos)
-    gk += gl1 * ((float)h[3] * fc - (float)h[0] * fs) + gl2 * ((float)h[4] * fc - (float)h[1] * fs) +
-          gl3 * ((float)h[5] * fc - (float)h[2] * fs);
+    const float uc = u * fc, us = u * fs;
+    gHu[0] = fmaf(gl1, uc, gHu[0]);
+    gHu[1] = fmaf(gl2, uc, gHu[1]);
+    gHu[2] = fmaf(gl3, uc, gHu[2]);
+    gHu[3] = fmaf(gl1, us, gHu[3]);
+    gHu[4] = fmaf(gl2, us, gHu[4]);
+    gHu[5] = fmaf(gl3, us, gHu[5]);
+}
+
+// Sum over planes of gk dl/dkappa . dE/dl with dl/dkappa = H (-sin, cos):
+// from the accumulated sums G_c = sum gl cos, G_s = sum gl sin,
+//   sum gk = H_s . G_c - H_c . G_s   (H_c = h[0..2], H_s = h[3..5]).
+template <class G>
+__device__ __forceinline__ float kappa_sum(const G h[6], const float gH[6]) {
+    float r = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r = fmaf((float)h[3 + i], gH[i], fmaf(-(float)h[i], gH[3 + i], r));
+    return r;
 }
 
 constexpr int kSens = 14;  // per-pair sensitivities: dE/dHa [6], dE/dHb [6], two for the arc
@@ -182,6 +203,8 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         int cnt = 0;
         float g[kSens];
         for (int i = 0; i < kSens; ++i) g[i] = 0.0f;
+        float gu[12];  // dE/dHa, dE/dHb terms weighted by the plane position u
+        for (int i = 0; i < 12; ++i) gu[i] = 0.0f;
         G sn, cs;
         g_sincos(pc.k0 + (G)lane * pc.dk, &sn, &cs);
         for (int i = 0; i < n_sweeps; ++i) {
@@ -196,18 +219,23 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                 const float diff = sample_taps<Tap, G>(ca, ta, pc.inv_f2a, pc.sa) -
                                    sample_taps<Tap, G>(cb, tb, pc.inv_f2b, pc.sb);
                 acc = fmaf(diff, diff, acc);
-                float gk = 0.0f;
-                lookup_adjoint<Tap, G>(pc.ha, cs, sn, ta, ec, pc.inv_f2a, pc.sa, diff, ca, g, gk);
-                lookup_adjoint<Tap, G>(pc.hb, cs, sn, tb, ec, pc.inv_f2b, pc.sb, -diff, cb, g + 6, gk);
                 // object sphere: kappa_k = kappa_max ((2k + 1) / K - 1);
                 // detector arc: kappa_k = lo + u (hi - lo), u = (k + 1/2) / K
                 const float u = ((float)(lane + 64 * i) + 0.5f) * kinv;
-                g[12] = fmaf(gk, detector ? 1.0f - u : 2.0f * u - 1.0f, g[12]);
-                g[13] = fmaf(gk, detector ? u : 0.0f, g[13]);
+                lookup_adjoint<Tap, G>(cs, sn, ta, ec, pc.inv_f2a, pc.sa, diff, ca, u, g, gu);
+                lookup_adjoint<Tap, G>(cs, sn, tb, ec, pc.inv_f2b, pc.sb, -diff, cb, u, g + 6, gu + 6);
             }
             const G c2 = cs * pc.rc - sn * pc.rs;
             sn = sn * pc.rc + cs * pc.rs;
             cs = c2;
+        }
+        {
+            // dE/dkappa_k summed with the weights of the range's parameters:
+            // object sphere, kappa_max: 2u - 1; detector arc, lo: 1 - u, hi: u
+            const float s0 = kappa_sum(pc.ha, g) + kappa_sum(pc.hb, g + 6);
+            const float s1 = kappa_sum(pc.ha, gu) + kappa_sum(pc.hb, gu + 6);
+            g[12] = detector ? s0 - s1 : fmaf(2.0f, s1, -s0);
+            g[13] = detector ? s1 : 0.0f;
         }
         acc = wave_sum(acc);
         const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
