@@ -276,7 +276,8 @@ __device__ __forceinline__ float bp_cell(float x, float hi, int &i) {
 }
 
 // The part of one padded filtered view that a workgroup's 16 x 16 x 16 voxel
-// box reads: element rows [v_lo, v_lo + rows) x columns [u_lo, u_lo + cols).
+// box reads: element rows [v_lo, v_lo + rows) x columns [u_lo, u_lo + cols), returned as
+// (u_lo, v_lo, rows, cols).
 // The box lies in front of the source, so its projection is the convex hull
 // of its 8 corner voxels' projections.  One cell of margin on each side
 // covers the rounding of the per-voxel coordinates; the cell indices are
@@ -284,7 +285,7 @@ __device__ __forceinline__ float bp_cell(float x, float hi, int &i) {
 // cell's second column (also when the whole box projects past the
 // detector's edge).  cols = 0 when a corner is not in front of the source or
 // the window exceeds the LDS tile (the view is then read directly).
-__device__ __forceinline__ short4 bp_window(const FdkView &w, float xb, float yb, float zb, float ext, int W,
+__device__ __forceinline__ int4 bp_window(const FdkView &w, float xb, float yb, float zb, float ext, int W,
                                             int H) {
     float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, cmin = INFINITY;
 #pragma unroll
@@ -307,8 +308,8 @@ __device__ __forceinline__ short4 bp_window(const FdkView &w, float xb, float yb
     const float vlo = __builtin_amdgcn_fmed3f(floorf(vmin) - 1.0f, 0.0f, (float)(H + 2));
     const float vhi = __builtin_amdgcn_fmed3f(floorf(vmax) + 1.0f, 0.0f, (float)(H + 2));
     const bool fits = cmin > 0.0f && uhi - ulo < (float)kBpCols && vhi - vlo < (float)kBpRows;
-    if (!fits) return make_short4(0, 0, 0, 0);
-    return make_short4((short)ulo, (short)vlo, (short)(vhi - vlo + 1.0f), (short)(uhi - ulo + 1.0f));
+    if (!fits) return make_int4(0, 0, 0, 0);
+    return make_int4((int)ulo, (int)vlo, (int)(vhi - vlo + 1.0f), (int)(uhi - ulo + 1.0f));
 }
 
 // Workgroups are numbered so that each XCD (8 per chip, blocks dealt to them
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
                                                               int W, int H, FdkVolume vol, int tiles_x, int tiles_y,
                                                               int n_tiles, float *__restrict__ out) {
     __shared__ float2 win_lds[kBpRows * kBpPitch];
-    __shared__ short4 wins[2][kBpWinChunk];  // windows of two chunks of views
+    __shared__ int4 wins[2][kBpWinChunk];  // windows of two chunks of views
     const int per = (n_tiles + 7) / 8;
     const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (tile >= n_tiles) return;  // no barrier has been reached yet
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
     // staging: wave w moves window rows w + 4 i, lane l their column l
     const int sw = __builtin_amdgcn_readfirstlane(wave);
     float2 pre[kBpPer];
-    auto prefetch = [&](const short4 &wn, int view) {
+    auto prefetch = [&](const int4 &wn, int view) {
         const float2 *src = Qi + view * view_elems + (int64_t)(wn.y + sw) * WP + wn.x;
         if (lane < wn.w) {
 #pragma unroll
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
                 if (sw + 4 * i < wn.z) pre[i] = src[(uint32_t)(4 * i) * WP + lane];
         }
     };
-    auto stage = [&](const short4 &wn) {
+    auto stage = [&](const int4 &wn) {
         if (lane < wn.w) {
 #pragma unroll
             for (int i = 0; i < kBpPer; ++i)
@@ -378,9 +379,9 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
         if (v < n_views) wins[c & 1][threadIdx.x] = bp_window(views[v], xb, yb, z0, ext, W, H);
     };
     auto window_of = [&](int v) {
-        const short4 r = wins[(v / kBpWinChunk) & 1][v % kBpWinChunk];
-        return make_short4((short)__builtin_amdgcn_readfirstlane(r.x), (short)__builtin_amdgcn_readfirstlane(r.y),
-                           (short)__builtin_amdgcn_readfirstlane(r.z), (short)__builtin_amdgcn_readfirstlane(r.w));
+        const int4 r = wins[(v / kBpWinChunk) & 1][v % kBpWinChunk];
+        return make_int4(__builtin_amdgcn_readfirstlane(r.x), __builtin_amdgcn_readfirstlane(r.y),
+                         __builtin_amdgcn_readfirstlane(r.z), __builtin_amdgcn_readfirstlane(r.w));
     };
     // bilinear value of cell (iu, iv) at fractions (fu, fv), from the window
     // (FROM_LDS) or from the view
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
         return fmaf(fv, bot - top, top);
     };
     // the updates of one view; FROM_LDS is the same for the whole workgroup
-    auto view_updates = [&](const FdkView &w, const float2 *q, const short4 &wn, auto from_lds) {
+    auto view_updates = [&](const FdkView &w, const float2 *q, const int4 &wn, auto from_lds) {
         constexpr bool FROM_LDS = decltype(from_lds)::value;
         auto cell = [&](int iu, int iv, float fu, float fv) {
             fdk_f32x4_a8 t;
@@ -442,11 +443,11 @@ __global__ __launch_bounds__(256) void fdk_backproject_kernel(const float2 *__re
     };
     chunk_windows(0);
     __syncthreads();
-    short4 next = window_of(0);
+    int4 next = window_of(0);
     if (next.w) prefetch(next, 0);
     for (int j = 0; j < n_views; ++j) {
         const FdkView &w = views[j];
-        const short4 cur = next;
+        const int4 cur = next;
         // the next chunk's windows, written to the buffer whose last reads
         // (views of the chunk before this one) ended two barriers ago; the
         // barrier below orders them before their first read
