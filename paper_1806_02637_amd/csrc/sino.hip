@@ -110,13 +110,25 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 
 typedef float f32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 
+// Nonnegative position in pixels as a 32.32 fixed-point integer (a negative
+// step is its two's complement).
+__device__ __forceinline__ int64_t to_fixed(double x) { return (int64_t)llrint(ldexp(x, 32)); }
+
+// Fraction of a 32.32 position from its low word: the top 23 bits become the
+// mantissa of a float in [1, 2) (one funnel shift), minus 1 (exact).
+__device__ __forceinline__ float fixed_fraction(uint32_t lo) {
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, lo, 9u)) - 1.0f;
+}
+
 // Block = 4 waves; each wave sums kLinesPerWave consecutive lines (t_k) of
 // one alpha_m, one after the other.  For a line, lane l takes the samples
 // j = j_lo + l + 64 i of its clipped stretch [j_lo, j_hi]; positions are
-// carried in FP64 (one add per sample and axis, no drift), the pad offset
-// included so that they stay positive and truncation is the floor.  Each
-// lane sums up to 32 samples in FP32 before adding to its FP64 total; the 64
-// lane totals are added in a fixed butterfly order.
+// carried as 32.32 fixed-point integers (one 64-bit add per sample and axis;
+// the step is rounded to 2^-32 px, a drift below 1e-8 px over a line), the
+// pad offset included so that they stay positive: the high word is the
+// pixel, the low word's top 23 bits the bilinear weight.  Each lane sums up
+// to 32 samples in FP32 before adding to its FP64 total; the 64 lane totals
+// are added in a fixed butterfly order.
 constexpr int kLinesPerWave = 4;
 
 __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict__ gw2,
@@ -139,7 +151,7 @@ __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict
     const double dp = trans ? ca : -sa, dq = trans ? -sa : ca;
     const float *img = (trans ? gwT2 : gw2) + (int64_t)v * 2 * Wp * Hp;
     const double c = 0.5 * (n_s - 1);
-    const double step_p = 64.0 * ds * dp, step_q = 64.0 * ds * dq;
+    const int64_t fx_step_p = to_fixed(64.0 * ds * dp), fx_step_q = to_fixed(64.0 * ds * dq);
     // reciprocals for the clip: |dp| >= 1/sqrt(2) by the choice of copy, dq
     // may vanish (lines along an image axis)
     const double inv_dp = 1.0 / dp, inv_ds = 1.0 / ds;
@@ -171,12 +183,10 @@ __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict
         }
         n = __builtin_amdgcn_readfirstlane(max(n, 0));  // the same on every lane
         const double s = (j_lo + lane - c) * ds;
-        double pp = p0 + s * dp + kImgPad, qq = q0 + s * dq + kImgPad;
+        int64_t pp = to_fixed(p0 + s * dp + kImgPad), qq = to_fixed(q0 + s * dq + kImgPad);
         auto sample = [&]() {
-            // positions are positive: truncation is the floor, and the
-            // hardware fraction is pp - floor(pp)
-            const int ip = (int)pp, iq = (int)qq;
-            const float fp = (float)__builtin_amdgcn_fract(pp), fq = (float)__builtin_amdgcn_fract(qq);
+            const int ip = (int)(pp >> 32), iq = (int)(qq >> 32);
+            const float fp = fixed_fraction((uint32_t)pp), fq = fixed_fraction((uint32_t)qq);
             const uint32_t e = __umul24((uint32_t)iq, (uint32_t)pitch) + (uint32_t)ip;
             const f32x4_a8 g = *(const f32x4_a8 *)((const char *)img + e * 8u);
             // g = (row iq, row iq + 1) at column ip, then at column ip + 1
@@ -192,8 +202,8 @@ __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict
 #pragma unroll 4
             for (int i = i0; i < i1; ++i) {
                 part += sample();
-                pp += step_p;
-                qq += step_q;
+                pp += fx_step_p;
+                qq += fx_step_q;
             }
             acc += (double)part;
         }
