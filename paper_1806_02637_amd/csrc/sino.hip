@@ -85,26 +85,12 @@ __device__ __forceinline__ void clip_axis_r(double c0, double inv_dc, double lo,
     s_hi = fmin(s_hi, fmax(a, b));
 }
 
-// Wave-wide FP64 sum in a fixed order (DPP on both halves: pairs, quads,
-// half rows, rows, then rows 0-1 and 0-3); lane 63 ends with the total,
-// returned to every lane.
+// FP64 value of another lane by DPP (two 32-bit moves).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_f64(double x) {
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double wave_sum_f64(double x) {
-    x += dpp_f64<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
-    x += dpp_f64<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
-    x += dpp_f64<0x141, 0xF>(x);  // row_half_mirror
-    x += dpp_f64<0x140, 0xF>(x);  // row_mirror
-    x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15
-    x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -120,16 +106,29 @@ __device__ __forceinline__ float fixed_fraction(uint32_t lo) {
     return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, lo, 9u)) - 1.0f;
 }
 
-// Block = 4 waves; each wave sums kLinesPerWave consecutive lines (t_k) of
-// one alpha_m, one after the other.  For a line, lane l takes the samples
-// j = j_lo + l + 64 i of its clipped stretch [j_lo, j_hi]; positions are
-// carried as 32.32 fixed-point integers (one 64-bit add per sample and axis;
-// the step is rounded to 2^-32 px, a drift below 1e-8 px over a line), the
-// pad offset included so that they stay positive: the high word is the
-// pixel, the low word's top 23 bits the bilinear weight.  Each lane sums up
-// to 32 samples in FP32 before adding to its FP64 total; the 64 lane totals
-// are added in a fixed butterfly order.
+// Block = 4 waves; each wave sums kLinesPerWave = 4 consecutive lines (t_k)
+// of one alpha_m at once, 16 lanes per line: lane l takes line l / 16 and
+// the samples j = j_lo + (l mod 16) + 16 i of that line's clipped stretch.
+// A gather thus covers a compact patch (16 samples along, 4 lines across)
+// of the image and touches few cache lines.  Positions are carried as 32.32
+// fixed-point integers (one 64-bit add per sample and axis; the step is
+// rounded to 2^-32 px, a drift below 1e-8 px over a line), the pad offset
+// included so that they stay positive: the high word is the pixel, the low
+// word's top 23 bits the bilinear weight.  Each lane sums up to 32 samples in
+// FP32 before adding to its FP64 total; the 16 lane totals of a line are
+// added in a fixed butterfly order.
 constexpr int kLinesPerWave = 4;
+constexpr int kLanesPerLine = 64 / kLinesPerWave;
+
+// Sum over the 16 lanes of a DPP row in a fixed order (pairs, quads, half
+// rows, rows); every lane of the row ends with the total.
+__device__ __forceinline__ double row_sum_f64(double x) {
+    x += dpp_f64<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141, 0xF>(x);  // row_half_mirror
+    x += dpp_f64<0x140, 0xF>(x);  // row_mirror
+    return x;
+}
 
 __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict__ gw2,
                                                          const float *__restrict__ gwT2,
@@ -151,66 +150,75 @@ __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict
     const double dp = trans ? ca : -sa, dq = trans ? -sa : ca;
     const float *img = (trans ? gwT2 : gw2) + (int64_t)v * 2 * Wp * Hp;
     const double c = 0.5 * (n_s - 1);
-    const int64_t fx_step_p = to_fixed(64.0 * ds * dp), fx_step_q = to_fixed(64.0 * ds * dq);
+    const int64_t fx_step_p = to_fixed(kLanesPerLine * ds * dp), fx_step_q = to_fixed(kLanesPerLine * ds * dq);
     // reciprocals for the clip: |dp| >= 1/sqrt(2) by the choice of copy, dq
     // may vanish (lines along an image axis)
     const double inv_dp = 1.0 / dp, inv_ds = 1.0 / ds;
     const bool q_flat = fabs(dq) < 1e-12;
     const double inv_dq = q_flat ? 0.0 : 1.0 / dq;
-    for (int li = 0; li < kLinesPerWave; ++li) {
-        const int k = (blockIdx.x * 4 + wave) * kLinesPerWave + li;
-        if (k >= n_t) break;  // wave-uniform
-        const double t = -t_max + k * dt;
-        const double p0 = trans ? v0 + t * sa : u0 + t * ca;
-        const double q0 = trans ? u0 + t * ca : v0 + t * sa;
-        double s_lo = -1e300, s_hi = 1e300;
-        clip_axis_r(p0, inv_dp, -1.0, (double)P_ext, s_lo, s_hi);
-        if (q_flat) {
-            if (!(q0 > -1.0 && q0 < (double)Q_ext)) {
-                s_lo = 1.0;
-                s_hi = -1.0;
-            }
-        } else {
-            clip_axis_r(q0, inv_dq, -1.0, (double)Q_ext, s_lo, s_hi);
+    // this lane's line and place in it
+    const int li = lane / kLanesPerLine, sl = lane % kLanesPerLine;
+    const int k = (blockIdx.x * 4 + wave) * kLinesPerWave + li;
+    const double t = -t_max + k * dt;
+    const double p0 = trans ? v0 + t * sa : u0 + t * ca;
+    const double q0 = trans ? u0 + t * ca : v0 + t * sa;
+    double s_lo = -1e300, s_hi = 1e300;
+    clip_axis_r(p0, inv_dp, -1.0, (double)P_ext, s_lo, s_hi);
+    if (q_flat) {
+        if (!(q0 > -1.0 && q0 < (double)Q_ext)) {
+            s_lo = 1.0;
+            s_hi = -1.0;
         }
-        int n = 0, j_lo = 0;
-        if (s_lo <= s_hi) {
-            // one extra sample (ds <= 1 px) on each side absorbs rounding of
-            // the clip: samples stay within 2 px of the image, inside the
-            // zero border
-            j_lo = max(0, (int)ceil(s_lo * inv_ds + c) - 1);
-            n = min(n_s - 1, (int)floor(s_hi * inv_ds + c) + 1) - j_lo + 1;
-        }
-        n = __builtin_amdgcn_readfirstlane(max(n, 0));  // the same on every lane
-        const double s = (j_lo + lane - c) * ds;
-        int64_t pp = to_fixed(p0 + s * dp + kImgPad), qq = to_fixed(q0 + s * dq + kImgPad);
-        auto sample = [&]() {
-            const int ip = (int)(pp >> 32), iq = (int)(qq >> 32);
-            const float fp = fixed_fraction((uint32_t)pp), fq = fixed_fraction((uint32_t)qq);
-            const uint32_t e = __umul24((uint32_t)iq, (uint32_t)pitch) + (uint32_t)ip;
-            const f32x4_a8 g = *(const f32x4_a8 *)((const char *)img + e * 8u);
-            // g = (row iq, row iq + 1) at column ip, then at column ip + 1
-            const float a = fmaf(fp, g.z - g.x, g.x);
-            const float b = fmaf(fp, g.w - g.y, g.y);
-            return fmaf(fq, b - a, a);
-        };
-        double acc = 0.0;
-        const int n_full = n >> 6;  // sweeps in which every lane has a sample (wave-uniform)
-        for (int i0 = 0; i0 < n_full; i0 += 32) {
-            const int i1 = min(i0 + 32, n_full);
-            float part = 0.0f;
-#pragma unroll 4
-            for (int i = i0; i < i1; ++i) {
-                part += sample();
-                pp += fx_step_p;
-                qq += fx_step_q;
-            }
-            acc += (double)part;
-        }
-        if (lane < (n & 63)) acc += (double)sample();
-        acc = wave_sum_f64(acc);
-        if (lane == 0) G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
+    } else {
+        clip_axis_r(q0, inv_dq, -1.0, (double)Q_ext, s_lo, s_hi);
     }
+    int n = 0, j_lo = 0;  // the same on the line's 16 lanes
+    if (k < n_t && s_lo <= s_hi) {
+        // one extra sample (ds <= 1 px) on each side absorbs rounding of the
+        // clip: samples stay within 2 px of the image, inside the zero border
+        j_lo = max(0, (int)ceil(s_lo * inv_ds + c) - 1);
+        n = max(0, min(n_s - 1, (int)floor(s_hi * inv_ds + c) + 1) - j_lo + 1);
+    }
+    // sweeps in which every lane of the wave has a sample, and in which some do
+    int n_min = n, n_max = n;
+    n_min = min(n_min, __shfl_xor(n_min, 16, 64));
+    n_min = min(n_min, __shfl_xor(n_min, 32, 64));
+    n_max = max(n_max, __shfl_xor(n_max, 16, 64));
+    n_max = max(n_max, __shfl_xor(n_max, 32, 64));
+    const int full = __builtin_amdgcn_readfirstlane(n_min / kLanesPerLine);
+    const int sweeps = __builtin_amdgcn_readfirstlane((n_max + kLanesPerLine - 1) / kLanesPerLine);
+    const double s = (j_lo + sl - c) * ds;
+    int64_t pp = to_fixed(p0 + s * dp + kImgPad), qq = to_fixed(q0 + s * dq + kImgPad);
+    auto sample = [&]() {
+        const int ip = (int)(pp >> 32), iq = (int)(qq >> 32);
+        const float fp = fixed_fraction((uint32_t)pp), fq = fixed_fraction((uint32_t)qq);
+        const uint32_t e = __umul24((uint32_t)iq, (uint32_t)pitch) + (uint32_t)ip;
+        const f32x4_a8 g = *(const f32x4_a8 *)((const char *)img + e * 8u);
+        // g = (row iq, row iq + 1) at column ip, then at column ip + 1
+        const float a = fmaf(fp, g.z - g.x, g.x);
+        const float b = fmaf(fp, g.w - g.y, g.y);
+        return fmaf(fq, b - a, a);
+    };
+    double acc = 0.0;
+    for (int i0 = 0; i0 < full; i0 += 32) {
+        const int i1 = min(i0 + 32, full);
+        float part = 0.0f;
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i) {
+            part += sample();
+            pp += fx_step_p;
+            qq += fx_step_q;
+        }
+        acc += (double)part;
+    }
+    // the lines' ragged ends (adjacent lines differ by a few samples)
+    for (int i = full; i < sweeps; ++i) {
+        if (sl + kLanesPerLine * i < n) acc += (double)sample();
+        pp += fx_step_p;
+        qq += fx_step_q;
+    }
+    acc = row_sum_f64(acc);
+    if (sl == 0 && k < n_t) G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
 }
 
 hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *intr, int n_views, int W, int H,
