@@ -93,8 +93,10 @@ ecc_status ecc_scan_load(ecc_ctx *ctx, int32_t *scan_id, int32_t n_views, int32_
  * integrals.  dtype selects the storage (ECC_F32 / ECC_BF16 / ECC_F16; FP16
  * is stored with an exact per-view power-of-two scale).  Runs on `stream`
  * and synchronises it before returning; the projections are then released.
- * Errors: ECC_E_ARG (n_alpha < 2, n_t < 3, ds_px <= 0, bad dtype),
- * ECC_E_STATE (already built), ECC_E_NOSCAN, ECC_E_BUDGET, ECC_E_HIP. */
+ * Errors: ECC_E_ARG (n_alpha outside [2, 65536], n_t outside [3, 65536],
+ * (n_alpha + 1)(n_t + 2) >= 2^28 stored elements per view, ds_px outside
+ * (0, 1], bad dtype), ECC_E_STATE (already built), ECC_E_NOSCAN,
+ * ECC_E_BUDGET, ECC_E_HIP. */
 ecc_status ecc_scan_build_sinograms(ecc_ctx *ctx, int32_t scan_id, int32_t n_alpha, int32_t n_t,
                                     double ds_px, int32_t dtype, void *stream);
 
