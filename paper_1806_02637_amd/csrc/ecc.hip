@@ -341,10 +341,10 @@ static hipError_t launch_fwd_t(const void *sino, const void *table, EvalConsts e
 
 hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
                           double *partials, int n_tiles, hipStream_t s) {
-    if (ec.geom64) {
-        if (dtype == 0) return launch_fwd_v<TapF32, double, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
-        if (dtype == 1) return launch_fwd_v<TapBF16, double, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
-        return launch_fwd_v<TapF16, double, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
+    if (ec.geom64) {  // two planes' gathers in flight here too (1.5 % faster than one)
+        if (dtype == 0) return launch_fwd_v<TapF32, double, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
+        if (dtype == 1) return launch_fwd_v<TapBF16, double, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
+        return launch_fwd_v<TapF16, double, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
     }
     if (dtype == 0) return launch_fwd_t<TapF32, float>(sino, table, ec, out_pair, partials, n_tiles, s);
     if (dtype == 1) return launch_fwd_t<TapBF16, float>(sino, table, ec, out_pair, partials, n_tiles, s);
