@@ -120,13 +120,17 @@ __device__ __forceinline__ float fixed_fraction(uint32_t lo) {
 constexpr int kLinesPerWave = 4;
 constexpr int kLanesPerLine = 64 / kLinesPerWave;
 
-// Sum over the 16 lanes of a DPP row in a fixed order (pairs, quads, half
-// rows, rows); every lane of the row ends with the total.
-__device__ __forceinline__ double row_sum_f64(double x) {
-    x += dpp_f64<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
-    x += dpp_f64<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
-    x += dpp_f64<0x141, 0xF>(x);  // row_half_mirror
-    x += dpp_f64<0x140, 0xF>(x);  // row_mirror
+// Sum over each group of LANES consecutive lanes (4, 8, 16 or 32) in a fixed
+// order (pairs, quads, half rows, rows, row pairs); the total ends in the
+// group's last lane (in every lane of a group of at most 16).
+template <int LANES>
+__device__ __forceinline__ double group_sum_f64(double x) {
+    static_assert(LANES == 4 || LANES == 8 || LANES == 16 || LANES == 32, "group of 4 to 32 lanes");
+    x += dpp_f64<0xB1, 0xF>(x);                        // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E, 0xF>(x);                        // quad_perm [2,3,0,1]
+    if (LANES >= 8) x += dpp_f64<0x141, 0xF>(x);       // row_half_mirror
+    if (LANES >= 16) x += dpp_f64<0x140, 0xF>(x);      // row_mirror
+    if (LANES >= 32) x += dpp_f64<0x142, 0xA>(x);      // row_bcast:15 into rows 1 and 3
     return x;
 }
 
@@ -181,10 +185,10 @@ __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict
     }
     // sweeps in which every lane of the wave has a sample, and in which some do
     int n_min = n, n_max = n;
-    n_min = min(n_min, __shfl_xor(n_min, 16, 64));
-    n_min = min(n_min, __shfl_xor(n_min, 32, 64));
-    n_max = max(n_max, __shfl_xor(n_max, 16, 64));
-    n_max = max(n_max, __shfl_xor(n_max, 32, 64));
+    for (int o = kLanesPerLine; o < 64; o <<= 1) {
+        n_min = min(n_min, __shfl_xor(n_min, o, 64));
+        n_max = max(n_max, __shfl_xor(n_max, o, 64));
+    }
     const int full = __builtin_amdgcn_readfirstlane(n_min / kLanesPerLine);
     const int sweeps = __builtin_amdgcn_readfirstlane((n_max + kLanesPerLine - 1) / kLanesPerLine);
     const double s = (j_lo + sl - c) * ds;
@@ -217,8 +221,8 @@ __global__ __launch_bounds__(256) void sino_radon_kernel(const float *__restrict
         pp += fx_step_p;
         qq += fx_step_q;
     }
-    acc = row_sum_f64(acc);
-    if (sl == 0 && k < n_t) G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
+    acc = group_sum_f64<kLanesPerLine>(acc);
+    if (sl == kLanesPerLine - 1 && k < n_t) G[((int64_t)v * n_alpha + m) * n_t + k] = acc * ds;
 }
 
 hipError_t launch_sino_radon(const float *gw, const float *gwT, const double *intr, int n_views, int W, int H,
