@@ -168,6 +168,18 @@ __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const View
 // factor in front is one number per pair, so the sweep accumulates
 // (S_a - S_b) d(S_a - S_b) alongside the cost and the factor is applied
 // after the wave sums (no second sweep re-deriving the lines).
+// Waves of a workgroup: kWavesPerBlock / Q hypotheses of one pair tile, each
+// tile's pairs split into Q parts, Q = adj_pair_split(B).  With fewer
+// hypotheses than waves the spare waves take parts of the same tiles, so that
+// a B = 1 evaluation (one L-BFGS step) has four times the waves in flight it
+// would have with one wave per tile; the parts' sums are added in a fixed
+// order.
+__host__ __device__ inline int adj_pair_split(int B) { return B == 1 ? 4 : (B == 2 ? 2 : 1); }
+__host__ __device__ inline int64_t adj_work_items(int B, int n_tiles) {
+    const int hpb = kWavesPerBlock / adj_pair_split(B);
+    return (int64_t)n_tiles * ((B + hpb - 1) / hpb);
+}
+
 template <class Tap, class G>
 __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ sino,
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
@@ -175,13 +187,18 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                                                       int n_tiles) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int hyp_groups = (ec.B + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t total = (int64_t)n_tiles * hyp_groups;
+    const int Q = adj_pair_split(ec.B), hpb = kWavesPerBlock / Q;
+    const int hyp_groups = (ec.B + hpb - 1) / hpb;
+    const int64_t total = adj_work_items(ec.B, n_tiles);
     const int64_t w = xcd_work_item(total);
-    if (w >= total) return;
+    if (w >= total) return;  // whole workgroups
     const int tile = (int)(w / hyp_groups);
-    const int hyp = (int)(w % hyp_groups) * kWavesPerBlock + wave;
-    if (hyp >= ec.B) return;  // no barriers in this kernel
+    const int hyp = (int)(w % hyp_groups) * hpb + wave % hpb;
+    const int part = wave / hpb, q_per = kPairsPerWave / Q;
+    // a wave without a hypothesis exists only when Q = 1, where no barrier
+    // follows; with Q > 1 every wave has one (hpb = B)
+    if (hyp >= ec.B) return;
+    __shared__ double part_acc[kWavesPerBlock];
     __shared__ PairConst<G> slots[kWavesPerBlock][kPairsPerWave];
     stage_tile(slots[wave], table + (int64_t)hyp * ec.n_pairs, tile, lane, ec.n_views);
 
@@ -193,7 +210,7 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
     const bool in_tail = lane < (ec.K & 63);
     const uint64_t tail_mask = (1ull << (ec.K & 63)) - 1;
     double wave_acc = 0.0;
-    for (int q = 0; q < kPairsPerWave; ++q) {
+    for (int q = part * q_per; q < (part + 1) * q_per; ++q) {
         const PairConst<G> pc = uniform(slots[wave][q]);
         if (pc.va < 0) continue;
         const int64_t p = pair_index(pc.va, pc.vb, ec.n_views);
@@ -249,7 +266,17 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
             for (int i = 0; i < kSens; ++i) out[i] = g[i];
         }
     }
-    if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
+    if (Q == 1) {
+        if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
+    } else {
+        if (lane == 0) part_acc[wave] = wave_acc;
+        __syncthreads();
+        if (part == 0 && lane == 0) {
+            double sum = 0.0;
+            for (int k = 0; k < Q; ++k) sum += part_acc[k * hpb + wave];
+            partials[(int64_t)hyp * n_tiles + tile] = sum;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void pair_tangent_kernel(const ViewGeom *__restrict__ vt,
@@ -272,7 +299,7 @@ __global__ __launch_bounds__(256) void pair_tangent_kernel(const ViewGeom *__res
 template <class Tap, class G>
 static hipError_t launch_adj_t(const void *sino, const void *table, EvalConsts ec, float *sens, double *partials,
                                int n_tiles, hipStream_t s) {
-    const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
+    const int64_t total = adj_work_items(ec.B, n_tiles);
     const int64_t blocks = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL((ecc_adj_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
                        occupancy_lds_bytes(sizeof(PairConst<G>) * kPairsPerWave * kWavesPerBlock), s, sino,
