@@ -168,18 +168,6 @@ __device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const View
 // factor in front is one number per pair, so the sweep accumulates
 // (S_a - S_b) d(S_a - S_b) alongside the cost and the factor is applied
 // after the wave sums (no second sweep re-deriving the lines).
-// Waves of a workgroup: kWavesPerBlock / Q hypotheses of one pair tile, each
-// tile's pairs split into Q parts, Q = adj_pair_split(B).  With fewer
-// hypotheses than waves the spare waves take parts of the same tiles, so that
-// a B = 1 evaluation (one L-BFGS step) has four times the waves in flight it
-// would have with one wave per tile; the parts' sums are added in a fixed
-// order.
-__host__ __device__ inline int adj_pair_split(int B) { return B == 1 ? 4 : (B == 2 ? 2 : 1); }
-__host__ __device__ inline int64_t adj_work_items(int B, int n_tiles) {
-    const int hpb = kWavesPerBlock / adj_pair_split(B);
-    return (int64_t)n_tiles * ((B + hpb - 1) / hpb);
-}
-
 template <class Tap, class G>
 __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ sino,
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
@@ -187,9 +175,9 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                                                       int n_tiles) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int Q = adj_pair_split(ec.B), hpb = kWavesPerBlock / Q;
+    const int Q = pair_split(ec.B), hpb = kWavesPerBlock / Q;
     const int hyp_groups = (ec.B + hpb - 1) / hpb;
-    const int64_t total = adj_work_items(ec.B, n_tiles);
+    const int64_t total = plane_work_items(ec.B, n_tiles);
     const int64_t w = xcd_work_item(total);
     if (w >= total) return;  // whole workgroups
     const int tile = (int)(w / hyp_groups);
@@ -299,10 +287,10 @@ __global__ __launch_bounds__(256) void pair_tangent_kernel(const ViewGeom *__res
 template <class Tap, class G>
 static hipError_t launch_adj_t(const void *sino, const void *table, EvalConsts ec, float *sens, double *partials,
                                int n_tiles, hipStream_t s) {
-    const int64_t total = adj_work_items(ec.B, n_tiles);
+    const int64_t total = plane_work_items(ec.B, n_tiles);
     const int64_t blocks = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL((ecc_adj_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                       occupancy_lds_bytes(sizeof(PairConst<G>) * kPairsPerWave * kWavesPerBlock), s, sino,
+                       occupancy_lds_bytes(plane_kernel_lds<G>(), kAdjBlocksPerCU), s, sino,
                        (const PairConst<G> *)table, ec, sens, partials, n_tiles);
     return hipGetLastError();
 }

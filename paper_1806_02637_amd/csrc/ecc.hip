@@ -183,7 +183,8 @@ __device__ __forceinline__ void combine_plane(const PlaneInFlight &P, bool valid
 }
 
 // A wave = one hypothesis x one pair tile; a workgroup = 4 hypotheses of the
-// same tile (they read nearly the same sinogram cells).  UNIFORM moves the
+// same tile (they read nearly the same sinogram cells), or with B <= 2 the
+// hypotheses' tile split into parts over the 4 waves (pair_split).  UNIFORM moves the
 // pair constants from LDS into scalar registers.  Lanes walk the planes
 // k = lane + 64 i; the trip count is wave-uniform (K / 64 full sweeps plus a
 // masked tail) and the hit count is a population count of the hit mask.
@@ -199,13 +200,18 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     asm volatile("" : "+v"(ec.t0_tau));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int hyp_groups = (ec.B + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t total = (int64_t)n_tiles * hyp_groups;
+    const int Q = pair_split(ec.B), hpb = kWavesPerBlock / Q;
+    const int hyp_groups = (ec.B + hpb - 1) / hpb;
+    const int64_t total = plane_work_items(ec.B, n_tiles);
     const int64_t w = xcd_work_item(total);
-    if (w >= total) return;
+    if (w >= total) return;  // whole workgroups
     const int tile = (int)(w / hyp_groups);
-    const int hyp = (int)(w % hyp_groups) * kWavesPerBlock + wave;
-    if (hyp >= ec.B) return;  // no barriers in this kernel
+    const int hyp = (int)(w % hyp_groups) * hpb + wave % hpb;
+    const int part = wave / hpb, q_per = kPairsPerWave / Q;
+    // a wave without a hypothesis exists only when Q = 1, where no barrier
+    // follows; with Q > 1 every wave has one (hpb = B)
+    if (hyp >= ec.B) return;
+    __shared__ double part_acc[kWavesPerBlock];
     __shared__ PairConst<G> slots[kWavesPerBlock][kPairsPerWave];
     stage_tile(slots[wave], table + (int64_t)hyp * ec.n_pairs, tile, lane, ec.n_views);
 
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     const bool in_tail = lane < (ec.K & 63);
     const uint64_t tail_mask = (1ull << (ec.K & 63)) - 1;
     double wave_acc = 0.0;
-    for (int q = 0; q < kPairsPerWave; ++q) {
+    for (int q = part * q_per; q < (part + 1) * q_per; ++q) {
         const PairConst<G> pc = UNIFORM ? uniform(slots[wave][q]) : slots[wave][q];
         // view ids (and so the two sinogram bases) in scalar registers
         const int a = uniform(pc.va), b = uniform(pc.vb);
@@ -282,24 +288,33 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
         if (out_pair && lane == 0) out_pair[(int64_t)hyp * ec.n_pairs + p] = e;
         wave_acc += (double)e;
     }
-    if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
+    if (Q == 1) {
+        if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
+    } else {
+        if (lane == 0) part_acc[wave] = wave_acc;
+        __syncthreads();
+        if (part == 0 && lane == 0) {
+            double sum = 0.0;
+            for (int k = 0; k < Q; ++k) sum += part_acc[k * hpb + wave];
+            partials[(int64_t)hyp * n_tiles + tile] = sum;
+        }
+    }
 }
 
 // Occupancy cap of the plane kernels: workgroups per CU, enforced through an
 // unused dynamic LDS allocation (160 KB per CU).  More resident waves than
 // this widen the set of pair tiles in flight per XCD beyond what its L2 can
 // hold, and L2 misses grow faster than latency hiding gains.
-static int blocks_per_cu_cap() {
-    static int cap = [] {
+static int blocks_per_cu_cap(int default_cap) {
+    static int env = [] {
         const char *e = getenv("ECC_BLOCKS_PER_CU");
-        const int v = e ? atoi(e) : kDefaultBlocksPerCU;
-        return v < 0 ? 0 : v;
+        return e ? (atoi(e) < 0 ? 0 : atoi(e)) : -1;
     }();
-    return cap;
+    return env >= 0 ? env : default_cap;
 }
 
-size_t occupancy_lds_bytes(size_t static_bytes) {
-    const int cap = blocks_per_cu_cap();
+size_t occupancy_lds_bytes(size_t static_bytes, int default_cap) {
+    const int cap = blocks_per_cu_cap(default_cap);
     if (cap <= 0) return 0;
     size_t b = (160u * 1024u) / (size_t)cap;
     b = (b / 1024) * 1024;
@@ -310,10 +325,11 @@ size_t occupancy_lds_bytes(size_t static_bytes) {
 template <class Tap, class G, bool UNIFORM, bool PIPE>
 static hipError_t launch_fwd_v(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
                                int n_tiles, hipStream_t s) {
-    const int64_t total = (int64_t)n_tiles * ((ec.B + kWavesPerBlock - 1) / kWavesPerBlock);
+    const int64_t total = plane_work_items(ec.B, n_tiles);
     const int64_t blocks = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G, UNIFORM, PIPE>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                       occupancy_lds_bytes(sizeof(PairConst<G>) * kPairsPerWave * kWavesPerBlock), s, sino,
+                       occupancy_lds_bytes(plane_kernel_lds<G>(), sizeof(Tap) == 8 ? kFwdBlocksPerCU32 : kFwdBlocksPerCU16),
+                       s, sino,
                        (const PairConst<G> *)table, ec, out_pair, partials, n_tiles);
     return hipGetLastError();
 }

@@ -127,11 +127,16 @@ constexpr int kPairsPerWave = 64;
 // zero border (pixels) around the weighted projections read by the line sums
 constexpr int kImgPad = 3;
 constexpr int kWavesPerBlock = 4;
-// default cap on resident plane-kernel workgroups per CU (0 = no cap)
-constexpr int kDefaultBlocksPerCU = 4;
+// default caps on resident plane-kernel workgroups per CU (0 = no cap): the
+// forward kernel with 16-byte gathers (FP32 storage) 3, with 8-byte gathers
+// (BF16, FP16) 4, the adjoint 4
+constexpr int kFwdBlocksPerCU32 = 3;
+constexpr int kFwdBlocksPerCU16 = 4;
+constexpr int kAdjBlocksPerCU = 4;
 // default plane-loop variant of the FP32 forward kernel (see ecc.hip)
 constexpr int kDefaultFwdVariant = 4;
-// dynamic LDS that, added to a kernel's static LDS, enforces the cap
-size_t occupancy_lds_bytes(size_t static_bytes);
+// dynamic LDS that, added to a kernel's static LDS, enforces the cap (the
+// environment variable ECC_BLOCKS_PER_CU overrides default_cap)
+size_t occupancy_lds_bytes(size_t static_bytes, int default_cap);
 
 }  // namespace ecc

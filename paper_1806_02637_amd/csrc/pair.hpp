@@ -154,6 +154,25 @@ __device__ __forceinline__ void stage_tile(PairConst<G> *slots, const PairConst<
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Waves of a workgroup: kWavesPerBlock / Q hypotheses of one pair tile, each
+// tile's pairs split into Q parts, Q = pair_split(B).  With fewer
+// hypotheses than waves the spare waves take parts of the same tiles, so that
+// a B = 1 evaluation (one L-BFGS step) has four times the waves in flight it
+// would have with one wave per tile; the parts' sums are added in a fixed
+// order.
+__host__ __device__ inline int pair_split(int B) { return B == 1 ? 4 : (B == 2 ? 2 : 1); }
+__host__ __device__ inline int64_t plane_work_items(int B, int n_tiles) {
+    const int hpb = kWavesPerBlock / pair_split(B);
+    return (int64_t)n_tiles * ((B + hpb - 1) / hpb);
+}
+
+// Static LDS of the plane kernels: the pair constants of each wave's tile and
+// the per-wave partial sums.
+template <class G>
+constexpr size_t plane_kernel_lds() {
+    return sizeof(PairConst<G>) * kPairsPerWave * kWavesPerBlock + sizeof(double) * kWavesPerBlock;
+}
+
 // Logical work item of a block under the XCD-aware numbering.
 __device__ __forceinline__ int64_t xcd_work_item(int64_t total) {
     const int64_t per = (total + 7) / 8;
