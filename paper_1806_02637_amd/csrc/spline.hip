@@ -72,14 +72,15 @@ __global__ __launch_bounds__(256) void spline_motion_kernel(SplineKnots kn, int 
     theta[idx] = akima_at(kn, y, (double)lam);
 }
 
-// thread = (hypothesis, parameter, node): sum over the views the node
-// influences (segments j - 3 .. j + 2) of grad_theta * d theta / d y_j.
+// workgroup = (hypothesis, parameter, node): sum over the views the node
+// influences (segments j - 3 .. j + 2) of grad_theta * d theta / d y_j, the
+// views dealt over the 256 threads and the partial sums added in a fixed tree
+// order.
 __global__ __launch_bounds__(256) void spline_grad_kernel(SplineKnots kn, int B, int n_views,
                                                           const double *__restrict__ nodes,
                                                           const float *__restrict__ grad_theta,
                                                           double *__restrict__ grad_nodes) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)B * 6 * kn.n) return;
+    const int64_t idx = blockIdx.x;  // the grid holds exactly B * 6 * n workgroups
     const int j = (int)(idx % kn.n);
     const int64_t bc = idx / kn.n;
     const int c = (int)(bc % 6), b = (int)(bc / 6);
@@ -90,9 +91,16 @@ __global__ __launch_bounds__(256) void spline_grad_kernel(SplineKnots kn, int B,
     if (l0 < 0) l0 = 0;
     if (l1 > n_views - 1) l1 = n_views - 1;
     double acc = 0.0;
-    for (int lam = l0; lam <= l1; ++lam)
+    for (int lam = l0 + (int)threadIdx.x; lam <= l1; lam += blockDim.x)
         acc += (double)grad_theta[((int64_t)b * n_views + lam) * 6 + c] * akima_at(kn, y, (double)lam).d;
-    grad_nodes[idx] = acc;
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad_nodes[idx] = red[0];
 }
 
 }  // namespace
@@ -108,8 +116,8 @@ hipError_t launch_spline_motion(const SplineKnots &kn, int B, int n_views, const
 hipError_t launch_spline_grad(const SplineKnots &kn, int B, int n_views, const double *nodes,
                               const float *grad_theta, double *grad_nodes, hipStream_t s) {
     const int64_t n = (int64_t)B * 6 * kn.n;
-    hipLaunchKernelGGL(spline_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kn, B, n_views,
-                       nodes, grad_theta, grad_nodes);
+    hipLaunchKernelGGL(spline_grad_kernel, dim3((unsigned)n), dim3(256), 0, s, kn, B, n_views, nodes, grad_theta,
+                       grad_nodes);
     return hipGetLastError();
 }
 
