@@ -316,27 +316,34 @@ hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *v
 }
 
 // ---------------------------------------------------------------------------
-// grad[b][v][0..5] = sum over partners u (ascending) of the pair (min, max)'s
-// 12-vector: entries 0..5 when v is the first view of the pair, 6..11 else.
+// grad[b][v][0..5] = sum over partners u of the pair (min, max)'s 12-vector:
+// entries 0..5 when v is the first view of the pair, 6..11 else.  One wave
+// per (hypothesis, view): lane l adds the partners u = l, l + 64, ... in
+// FP64, then the 64 lane sums are added in a fixed butterfly order.
 __global__ __launch_bounds__(256) void reduce_grad_kernel(const float *__restrict__ pair_grad, int B, int n_views,
                                                           float *__restrict__ grad) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= B * n_views) return;
-    const int b = idx / n_views, v = idx % n_views;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wid >= (int64_t)B * n_views) return;  // whole waves; no barriers
+    const int b = (int)(wid / n_views), v = (int)(wid % n_views);
     const int64_t n_pairs = (int64_t)n_views * (n_views - 1) / 2;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const float *pg = pair_grad + (int64_t)b * n_pairs * 12;
-    for (int u = 0; u < n_views; ++u) {
+    for (int u = lane; u < n_views; u += 64) {
         if (u == v) continue;
         const float *src = u < v ? pg + pair_index(u, v, n_views) * 12 + 6 : pg + pair_index(v, u, n_views) * 12;
         for (int q = 0; q < 6; ++q) acc[q] += (double)src[q];
     }
-    for (int q = 0; q < 6; ++q) grad[(int64_t)idx * 6 + q] = (float)acc[q];
+    for (int q = 0; q < 6; ++q)
+        for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+    if (lane == 0)
+        for (int q = 0; q < 6; ++q) grad[wid * 6 + q] = (float)acc[q];
 }
 
 hipError_t launch_reduce_grad(const float *pair_grad, int B, int n_views, float *grad, hipStream_t s) {
-    const int n = B * n_views;
-    hipLaunchKernelGGL(reduce_grad_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pair_grad, B, n_views, grad);
+    const int64_t waves = (int64_t)B * n_views;
+    hipLaunchKernelGGL(reduce_grad_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, pair_grad, B, n_views,
+                       grad);
     return hipGetLastError();
 }
 
