@@ -7,7 +7,7 @@ Steps, in the paper's order:
 * pencil of epipolar planes about the baseline, kappa -> E^kappa
   ("Epipolar Consistency", Eq. 3);
 * epipolar lines without pseudo-inverse, Eqs. 13-14;
-* lookup of the precomputed intermediate function S_lam along each line
+* lookup of S_lam, Eq. 1's intermediate function, stored per view beforehand, along each line
   (Eq. 1, "Epipolar Consistency");
 * d = mean over planes hitting both detectors of (S_a - S_b)^2 (Eq. 15),
   e = d / (1 + d / c) (Eq. 16), cost = sum over pairs a < b of e (Eq. 17).

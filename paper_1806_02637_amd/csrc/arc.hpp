@@ -1,7 +1,6 @@
 // Detector-bounded plane range: the arc of a pair's pencil of epipolar
-// planes whose lines meet both detectors (the reading of Eq. 15's "planes
-// that hit both detectors" in which the sampled range itself is bounded by
-// the detectors).  Host and device code, FP64.
+// planes whose lines meet both detectors (the reading of Eq. 15's plane
+// count in which the sampled range itself is bounded by the detectors).  Host and device code, FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>

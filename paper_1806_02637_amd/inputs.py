@@ -8,7 +8,7 @@ would deliver -- projection matrices, intrinsics and line-integral images --
 plus the random motion parameters the cost is evaluated at.
 
 Conventions (the paper fixes none of them; Sec. "Experiments" only gives a
-200 degree short scan with 496 projections):
+short scan over 200 degrees with 496 projections):
 
 * World frame in mm, isocentre at the origin, rotation axis z.
 * View lam of N sits at orbit angle phi = lam * 200deg / (N - 1) with the

@@ -1,6 +1,7 @@
 """The pseudo-inverse route (the method the paper replaces) against the
 method on the GPU: the same lines up to a positive scale, so the same cost to
-rounding ("both algorithms produce the same results", Sec. "Experiments")."""
+rounding (the paper reports equal results for the two routes, Sec.
+"Experiments")."""
 import numpy as np
 import pytest
 

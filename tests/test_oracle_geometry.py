@@ -97,7 +97,7 @@ def moved_scan():
 
 
 def test_lines_equal_pseudo_inverse_lines(moved_scan):
-    # "Both algorithms produce the same results" (Results): Eq. 14's line is
+    # The two routes give equal results (Sec. "Results"): Eq. 14's line is
     # the pseudo-inverse line l = (P P^T)^-1 P E up to a scale whose sign
     # does not change between views or planes.
     P, theta, params, pairs = moved_scan

@@ -150,7 +150,7 @@ def test_sphere_matches_closed_form_with_grangeat_weight():
     weighted = (1 + t ** 2 / f ** 2)[None, :] * sino
     err_w = np.linalg.norm((weighted[:, ok] - refb)) / np.linalg.norm(refb)
     err_u = np.linalg.norm((sino[:, ok] - refb)) / np.linalg.norm(refb)
-    assert err_w < 0.01
+    assert err_w < 0.007  # 0.0054 measured; 0.0099 without the cosine weight
     assert err_u > 0.015  # the test sees a missing weight
     # isotropy: a centred sphere's sinogram does not depend on alpha
     assert np.abs(sino - sino.mean(0)).max() < 0.03 * np.abs(sino).max()
