@@ -163,6 +163,22 @@ ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *thet
                     const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
                     void *workspace_dev, uint64_t workspace_bytes, void *stream);
 
+/* ecc_cost for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving or optimiser loops, harnesses that forbid
+ * hipMalloc.  Same kernels, arguments and results as ecc_cost (bitwise), but
+ * the workspace is a static device array of 64 MiB per GPU
+ * (ECC_NOALLOC_SCRATCH_BYTES) that the library holds until the process ends;
+ * the call itself allocates nothing.  It rejects with ECC_E_ARG an
+ * evaluation whose workspace (ecc_workspace_bytes with with_grad = 0)
+ * exceeds that size, e.g. B > 3 hypotheses of a 496-view scan.  Every call
+ * on one GPU shares that GPU's array, so calls that overlap on the device
+ * (different streams, or different host threads) race and must be
+ * serialised by the caller; the array keeps the last call's contents, and
+ * nothing in it needs to start at zero.  Errors as ecc_cost. */
+#define ECC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+ecc_status ecc_cost_noalloc(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                            const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev, void *stream);
+
 /* Cost and its gradient with respect to every view's 6 motion parameters
  * (reverse sweep through Eqs. 13-16; the line geometry is recomputed, not
  * stored).  grad_dev [B][n_views][6] FP32 is overwritten.

@@ -18,13 +18,15 @@ ECC_OK, ECC_E_ARG, ECC_E_BUDGET, ECC_E_HIP, ECC_E_STATE, ECC_E_NOSCAN = 0, -1, -
 ECC_F32, ECC_BF16, ECC_F16 = 0, 1, 2
 ECC_GEOM_F32, ECC_GEOM_F64 = 0, 1
 ECC_KAPPA_OBJECT, ECC_KAPPA_DETECTOR = 0, 1
+ECC_NOALLOC_SCRATCH_BYTES = 64 << 20
 DTYPES = {"f32": ECC_F32, "bf16": ECC_BF16, "f16": ECC_F16}
 
 # every symbol include/ecc.h declares
 SYMBOLS = (
     "ecc_last_error", "ecc_create", "ecc_destroy", "ecc_scan_load", "ecc_scan_build_sinograms",
     "ecc_scan_set_sinograms", "ecc_scan_read_sinogram", "ecc_scan_free", "ecc_scan_bytes", "ecc_workspace_bytes",
-    "ecc_cost", "ecc_cost_grad", "ecc_cost_pinv", "ecc_scan_info", "ecc_spline_motion", "ecc_spline_motion_grad",
+    "ecc_cost", "ecc_cost_noalloc", "ecc_cost_grad", "ecc_cost_pinv", "ecc_scan_info", "ecc_spline_motion",
+    "ecc_spline_motion_grad",
     "ecc_fdk_workspace_bytes", "ecc_fdk",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_wait", "ecc_server_request_bytes",
     "ecc_server_set_work_cap", "ecc_server_destroy",
@@ -69,6 +71,7 @@ _SIGNATURES = {
     "ecc_scan_bytes": ([_P, _I32, ctypes.POINTER(_U64)], _I32),
     "ecc_workspace_bytes": ([_P, _I32, _I32, _I32, ctypes.POINTER(_U64)], _I32),
     "ecc_cost": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _U64, _P], _I32),
+    "ecc_cost_noalloc": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P], _I32),
     "ecc_cost_grad": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _P, _U64, _P], _I32),
     "ecc_cost_pinv": ([_P, _I32, _I32, _P, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _U64, _P], _I32),
     "ecc_scan_info": ([_P, _I32] + [ctypes.POINTER(_I32)] * 5, _I32),
@@ -166,6 +169,12 @@ def ecc_cost(ctx: int, scan_id: int, B: int, theta_ptr: int, params: EvalParams,
              out_pair_ptr: int, workspace_ptr: int, workspace_bytes: int, stream: int = 0):
     _check(load_library().ecc_cost(ctx, scan_id, B, theta_ptr, ctypes.byref(params), out_cost_ptr, out_pair_ptr,
                                    workspace_ptr, workspace_bytes, stream), "ecc_cost")
+
+
+def ecc_cost_noalloc(ctx: int, scan_id: int, B: int, theta_ptr: int, params: EvalParams, out_cost_ptr: int,
+                     out_pair_ptr: int, stream: int = 0):
+    _check(load_library().ecc_cost_noalloc(ctx, scan_id, B, theta_ptr, ctypes.byref(params), out_cost_ptr,
+                                           out_pair_ptr, stream), "ecc_cost_noalloc")
 
 
 def ecc_cost_grad(ctx: int, scan_id: int, B: int, theta_ptr: int, params: EvalParams, out_cost_ptr: int,

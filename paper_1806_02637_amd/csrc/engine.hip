@@ -62,6 +62,21 @@ struct Scan {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free cost entry point (ecc_cost_noalloc):
+// one array per GPU, held until the process ends.  Host code never uses the
+// array's name as an address: each device's copy is resolved once with
+// hipGetSymbolAddress (in ecc_create, with that device current) and only
+// that pointer is handed to kernels.
+constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
 struct ecc_ctx {
     int device = 0;
     uint64_t budget = 0, used = 0;
@@ -226,6 +241,22 @@ ecc_status ecc_create(ecc_ctx **out, int hip_device, uint64_t hbm_budget_bytes) 
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess) return fail(ECC_E_HIP, "hipGetDeviceCount failed: %s", hipGetErrorString(e));
     if (hip_device < 0 || hip_device >= n) return fail(ECC_E_ARG, "device %d not present (%d devices)", hip_device, n);
+    if (hip_device >= kMaxScratchDevices)
+        return fail(ECC_E_ARG, "device %d beyond the %d devices the engine supports", hip_device, kMaxScratchDevices);
+    {
+        // this device's copy of the no-alloc scratch, resolved once with the
+        // device current
+        DeviceGuard g(hip_device);
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[hip_device]) {
+            void *ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(ECC_E_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", hip_device,
+                            hipGetErrorString(e));
+            g_scratch_ptr[hip_device] = ptr;
+        }
+    }
     ecc_ctx *ctx = new ecc_ctx();
     ctx->device = hip_device;
     ctx->budget = hbm_budget_bytes;
@@ -662,6 +693,35 @@ static ecc_status cost_impl(ecc_ctx *ctx, int32_t scan_id, int32_t B, const doub
     HIP_TRY(launch_ecc_fwd(s->sino_dev, table, ec, s->layout.dtype, out_pair_dev, partials, n_tiles, hs));
     HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
     return ok();
+}
+
+ecc_status ecc_cost_noalloc(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                            const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev, void *stream) {
+    if (!ctx) return fail(ECC_E_ARG, "null context");
+    uint64_t need = 0;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Scan *s = find_scan(ctx, scan_id);
+        if (!s) return fail(ECC_E_NOSCAN, "unknown scan id %d", scan_id);
+        if (B < 1 || B > 65536) return fail(ECC_E_ARG, "B = %d out of range [1, 65536]", B);
+        need = workspace_layout(s, B, false).total;
+    }
+    if (need > kNoAllocScratchBytes)
+        return fail(ECC_E_ARG,
+                    "ecc_cost_noalloc: %d hypotheses of this scan need %llu bytes of scratch, more than the %llu "
+                    "bytes the static scratch holds (use ecc_cost with a caller workspace)",
+                    B, (unsigned long long)need, (unsigned long long)kNoAllocScratchBytes);
+    void *ptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ptr = g_scratch_ptr[ctx->device];
+    }
+    if (!ptr) return fail(ECC_E_STATE, "no-alloc scratch of device %d was not resolved", ctx->device);
+    // the scan may change between the size check and the evaluation only by
+    // ecc_scan_free, which cost_impl reports as ECC_E_NOSCAN; it checks the
+    // size again against the scratch it is given
+    return cost_impl(ctx, scan_id, B, theta_dev, nullptr, params, out_cost_dev, out_pair_dev, ptr,
+                     kNoAllocScratchBytes, stream);
 }
 
 ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
