@@ -129,9 +129,13 @@ def pencil(C_a, C_b, R_mm):
     w = [-C_a[i] + ca_b * bh[i] for i in range(3)]
     h = ops.sqrt(dot3(w, w))
     if float(_value(h)) < 1e-9:
+        # baseline through the isocentre: every plane of the pencil meets the
+        # sphere, kappa covers the whole half circle and u2 only fixes where
+        # the samples sit.  u2 = the part of the z axis (the orbit's rotation
+        # axis) perpendicular to the baseline, or of the x axis for a
+        # baseline within 60 degrees of z: a choice no rounding can tip
         bv = [float(_value(x)) for x in bh]
-        ax = min(range(3), key=lambda i: abs(bv[i]))
-        e = [1.0 if i == ax else 0.0 for i in range(3)]
+        e = [0.0, 0.0, 1.0] if abs(bv[2]) < 0.5 else [1.0, 0.0, 0.0]
         eb = dot3(e, bh)
         w = [e[i] - eb * bh[i] for i in range(3)]
         nw = ops.sqrt(dot3(w, w))

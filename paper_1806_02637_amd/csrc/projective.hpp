@@ -127,17 +127,13 @@ ECC_HD void pencil(const T Ca[3], const T Cb[3], double R_mm, T u1[3], T u2[3], 
     T w[3] = {cab * bh[0] - Ca[0], cab * bh[1] - Ca[1], cab * bh[2] - Ca[2]};
     T h = g_sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
     if (g_val(h) < 1e-9) {
-        // baseline through the isocentre: any plane of the pencil meets the
-        // sphere; pick u2 perpendicular to the baseline along the axis least
-        // aligned with it
-        int ax = 0;
-        double best = fabs(g_val(bh[0]));
-        for (int i = 1; i < 3; ++i)
-            if (fabs(g_val(bh[i])) < best) {
-                best = fabs(g_val(bh[i]));
-                ax = i;
-            }
-        T e[3] = {T(ax == 0 ? 1.0 : 0.0), T(ax == 1 ? 1.0 : 0.0), T(ax == 2 ? 1.0 : 0.0)};
+        // baseline through the isocentre: every plane of the pencil meets the
+        // sphere and kappa spans the half circle; u2 is the part of the z axis
+        // (the orbit's rotation axis) perpendicular to the baseline, or of the
+        // x axis for a baseline within 60 degrees of z, a threshold no
+        // rounding of the sources can tip
+        const bool use_z = fabs(g_val(bh[2])) < 0.5;
+        T e[3] = {T(use_z ? 0.0 : 1.0), T(0.0), T(use_z ? 1.0 : 0.0)};
         T eb = e[0] * bh[0] + e[1] * bh[1] + e[2] * bh[2];
         T ww[3] = {e[0] - eb * bh[0], e[1] - eb * bh[1], e[2] - eb * bh[2]};
         T nw = g_sqrt(ww[0] * ww[0] + ww[1] * ww[1] + ww[2] * ww[2]);

@@ -166,3 +166,24 @@ def test_pencil_planes_contain_both_sources_and_touch_sphere(moved_scan):
         assert dist.max() <= params.R_mm * (1 + 1e-12)
         km = float(g["kappa_max"])
         assert math.isclose(abs(g["kappa"][0]), km * (1 - 1.0 / params.K), rel_tol=1e-12)
+
+
+def test_baseline_through_isocentre_picks_a_stable_pencil():
+    # h < 1e-9: every plane of the pencil meets the sphere (kappa_max = pi/2)
+    # and u2 is the part of z perpendicular to the baseline (x for a baseline
+    # near z); rounding-level changes of the sources, which decide which
+    # near-zero component of the baseline direction is smaller, must not
+    # rotate the pencil
+    ref = None
+    for dy, dz in ((0.0, 0.0), (1e-13, -2e-13), (-3e-13, 1e-13), (2e-13, 2e-13)):
+        Ca, Cb = [785.0, 0.0, 0.0], [-785.0, dy, dz]
+        u1, u2, km = G.pencil(Ca, Cb, 90.0)
+        assert km == 0.5 * math.pi
+        u = np.array([u1, u2], dtype=float)
+        assert np.allclose(u @ u.T, np.eye(2), atol=1e-14)
+        assert np.allclose(u2, [0, 0, 1], atol=1e-12)
+        if ref is None:
+            ref = u
+        assert np.allclose(u, ref, atol=1e-12)
+    u1, u2, km = G.pencil([0.0, 1e-13, 785.0], [0.0, 0.0, -785.0], 90.0)
+    assert km == 0.5 * math.pi and np.allclose(u2, [1, 0, 0], atol=1e-12)
