@@ -68,18 +68,22 @@ ecc_status ecc_create(ecc_ctx **out, int hip_device, uint64_t hbm_budget_bytes);
 /* Frees every scan and the context.  Waits for the device to go idle. */
 ecc_status ecc_destroy(ecc_ctx *ctx);
 
-/* Loads one scan ("a configuration of ... projections described by their
- * projection matrix", Sec. "Epipolar Consistency").
+/* Loads one scan: a set of projections, each with its 3x4 projection
+ * matrix (Sec. "Epipolar Consistency").
  *   P      [n_views][3][4] FP64, row-major, maps world mm to detector pixels
  *          (pixel centres at integer (u, v), u = column, v = row).  All views
  *          must share the sign of det(P[:, :3]) (one detector handedness).
  *   intr   [n_views][3] FP64 = {f_px, u0, v0}: focal length in pixels and the
  *          principal point, used for the cosine weight of Eq. 1 and to centre
- *          detector lines.  Rigid motion does not change them.
+ *          detector lines.  The principal point must be the detector centre,
+ *          (u0, v0) = ((W - 1) / 2, (H - 1) / 2) within 1e-6 px: the hit test
+ *          behind Eq. 15's plane count and the sinogram's t range are taken
+ *          about it.  Rigid motion does not change them.
  *   images [n_views][H][W] FP32 line integrals (row v, column u); host memory
  *          if images_on_device == 0, else a device pointer.  Copied.
  * The projections are held (FP32, in HBM) until sinograms are built.
- * Errors: ECC_E_ARG (sizes < 2, NULLs, non-finite or mixed-handedness P),
+ * Errors: ECC_E_ARG (sizes < 2, NULLs, non-finite or mixed-handedness P,
+ * a principal point off the detector centre),
  * ECC_E_BUDGET, ECC_E_HIP. */
 ecc_status ecc_scan_load(ecc_ctx *ctx, int32_t *scan_id, int32_t n_views, int32_t W, int32_t H,
                          const double *P, const double *intr, const float *images, int32_t images_on_device);
@@ -162,6 +166,16 @@ ecc_status ecc_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, int32_t B, int32_t
 ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
                     const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
                     void *workspace_dev, uint64_t workspace_bytes, void *stream);
+
+/* ecc_cost plus the plane count of every pair: out_count_dev [B][n_pairs]
+ * int32 (device) = N_kappa of Eq. 15, the sampled planes whose lines hit both
+ * detectors (d = 0 when it is 0).  Lets a caller see how many planes carry a
+ * pair's term and compare the hit decisions of two precision forms.  Other
+ * arguments, the workspace and errors as ecc_cost (ECC_E_ARG for a NULL
+ * out_count_dev). */
+ecc_status ecc_cost_counts(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                           const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
+                           int32_t *out_count_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream);
 
 /* ecc_cost for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving or optimiser loops, harnesses that forbid

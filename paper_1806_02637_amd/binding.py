@@ -25,12 +25,14 @@ DTYPES = {"f32": ECC_F32, "bf16": ECC_BF16, "f16": ECC_F16}
 SYMBOLS = (
     "ecc_last_error", "ecc_create", "ecc_destroy", "ecc_scan_load", "ecc_scan_build_sinograms",
     "ecc_scan_set_sinograms", "ecc_scan_read_sinogram", "ecc_scan_free", "ecc_scan_bytes", "ecc_workspace_bytes",
-    "ecc_cost", "ecc_cost_noalloc", "ecc_cost_grad", "ecc_cost_pinv", "ecc_scan_info", "ecc_spline_motion",
-    "ecc_spline_motion_grad",
+    "ecc_cost", "ecc_cost_counts", "ecc_cost_noalloc", "ecc_cost_grad", "ecc_cost_pinv", "ecc_scan_info",
+    "ecc_spline_motion", "ecc_spline_motion_grad",
     "ecc_fdk_workspace_bytes", "ecc_fdk",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_wait", "ecc_server_request_bytes",
     "ecc_server_set_work_cap", "ecc_server_destroy",
 )
+# the measurement probe of include/ecc_probe.h
+PROBE_SYMBOLS = ("ecc_probe_gather",)
 
 
 class EccError(RuntimeError):
@@ -71,6 +73,7 @@ _SIGNATURES = {
     "ecc_scan_bytes": ([_P, _I32, ctypes.POINTER(_U64)], _I32),
     "ecc_workspace_bytes": ([_P, _I32, _I32, _I32, ctypes.POINTER(_U64)], _I32),
     "ecc_cost": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _U64, _P], _I32),
+    "ecc_cost_counts": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _P, _U64, _P], _I32),
     "ecc_cost_noalloc": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P], _I32),
     "ecc_cost_grad": ([_P, _I32, _I32, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _P, _U64, _P], _I32),
     "ecc_cost_pinv": ([_P, _I32, _I32, _P, _P, ctypes.POINTER(EvalParams), _P, _P, _P, _U64, _P], _I32),
@@ -87,6 +90,7 @@ _SIGNATURES = {
     "ecc_server_request_bytes": ([_P, _I32, _I32, _I32, ctypes.POINTER(_U64)], _I32),
     "ecc_server_set_work_cap": ([_P, ctypes.c_double], _I32),
     "ecc_server_destroy": ([_P], _I32),
+    "ecc_probe_gather": ([_P, _U64, _I32, _I32, _I32, _P, _P], _I32),
 }
 
 
@@ -169,6 +173,13 @@ def ecc_cost(ctx: int, scan_id: int, B: int, theta_ptr: int, params: EvalParams,
              out_pair_ptr: int, workspace_ptr: int, workspace_bytes: int, stream: int = 0):
     _check(load_library().ecc_cost(ctx, scan_id, B, theta_ptr, ctypes.byref(params), out_cost_ptr, out_pair_ptr,
                                    workspace_ptr, workspace_bytes, stream), "ecc_cost")
+
+
+def ecc_cost_counts(ctx: int, scan_id: int, B: int, theta_ptr: int, params: EvalParams, out_cost_ptr: int,
+                    out_pair_ptr: int, out_count_ptr: int, workspace_ptr: int, workspace_bytes: int, stream: int = 0):
+    _check(load_library().ecc_cost_counts(ctx, scan_id, B, theta_ptr, ctypes.byref(params), out_cost_ptr,
+                                          out_pair_ptr, out_count_ptr, workspace_ptr, workspace_bytes, stream),
+           "ecc_cost_counts")
 
 
 def ecc_cost_noalloc(ctx: int, scan_id: int, B: int, theta_ptr: int, params: EvalParams, out_cost_ptr: int,
@@ -259,3 +270,9 @@ def ecc_server_request_bytes(srv: int, scan_id: int, B: int, with_grad: int) -> 
 
 def ecc_server_destroy(srv: int):
     _check(load_library().ecc_server_destroy(srv), "ecc_server_destroy")
+
+
+def ecc_probe_gather(buf_ptr: int, nbytes: int, pattern: int, iters: int, n_blocks: int, out_ptr: int,
+                     stream: int = 0):
+    _check(load_library().ecc_probe_gather(buf_ptr, nbytes, pattern, iters, n_blocks, out_ptr, stream),
+           "ecc_probe_gather")

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libecc.so")
-SOURCES = ["sino.hip", "ecc.hip", "adj.hip", "spline.hip", "fdk.hip", "engine.hip", "server.hip"]
+SOURCES = ["sino.hip", "ecc.hip", "adj.hip", "spline.hip", "fdk.hip", "engine.hip", "server.hip", "probe.hip"]
 ARCH = os.environ.get("ECC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

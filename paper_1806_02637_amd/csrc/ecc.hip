@@ -7,7 +7,7 @@
 //              a table of per-plane constants.
 // ecc_fwd      a workgroup = 4 waves = 4 hypotheses of one tile of up to 64
 //              view pairs (8 x 8 view blocks); a wave walks its pairs
-//              (constants read with scalar loads) with lanes along the plane angle kappa: line ->
+//              (constants staged in LDS) with lanes along the plane angle kappa: line ->
 //              (alpha, t) -> four bilinear taps per view in one load ->
 //              (S_a - S_b)^2 -> wave-shuffle sum (Eq. 15) -> Cauchy norm
 //              (Eq. 16).  No atomics; per-tile FP64 partials.
@@ -19,7 +19,6 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
-#include <stdlib.h>
 
 #include "ecc_internal.hpp"
 #include "lookup.hpp"
@@ -184,17 +183,17 @@ __device__ __forceinline__ void combine_plane(const PlaneInFlight &P, bool valid
 
 // A wave = one hypothesis x one pair tile; a workgroup = 4 hypotheses of the
 // same tile (they read nearly the same sinogram cells), or with B <= 2 the
-// hypotheses' tile split into parts over the 4 waves (pair_split).  UNIFORM moves the
-// pair constants from LDS into scalar registers.  Lanes walk the planes
-// k = lane + 64 i; the trip count is wave-uniform (K / 64 full sweeps plus a
-// masked tail) and the hit count is a population count of the hit mask.
-// PIPE issues the gathers of sweep i + 1 before combining sweep i, so each
-// wave keeps two planes' gathers in flight.
-template <class Tap, class G, bool UNIFORM, bool PIPE>
+// hypotheses' tile split into parts over the 4 waves (pair_split).  Lanes
+// walk the planes k = lane + 64 i; the trip count is wave-uniform (K / 64
+// full sweeps plus a masked tail) and the hit count is a population count of
+// the hit mask.  The gathers of sweep i + 1 are issued before sweep i is
+// combined, so each wave keeps two planes' gathers in flight.  out_pair and
+// out_count (e and N_kappa per pair) are optional.
+template <class Tap, class G>
 __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ sino,
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
-                                                      float *__restrict__ out_pair, double *__restrict__ partials,
-                                                      int n_tiles) {
+                                                      float *__restrict__ out_pair, int32_t *__restrict__ out_count,
+                                                      double *__restrict__ partials, int n_tiles) {
     // the column offset joins an FMA with two other scalar operands: keep it
     // in a vector register for the whole kernel rather than copy it per plane
     asm volatile("" : "+v"(ec.t0_tau));
@@ -222,7 +221,7 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     const uint64_t tail_mask = (1ull << (ec.K & 63)) - 1;
     double wave_acc = 0.0;
     for (int q = part * q_per; q < (part + 1) * q_per; ++q) {
-        const PairConst<G> pc = UNIFORM ? uniform(slots[wave][q]) : slots[wave][q];
+        const PairConst<G> pc = slots[wave][q];
         // view ids (and so the two sinogram bases) in scalar registers
         const int a = uniform(pc.va), b = uniform(pc.vb);
         if (a < 0) continue;
@@ -245,7 +244,7 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
             const bool last = has_tail & (i == n_sweeps - 1);
             combine_plane(P, !last | in_tail, last ? tail_mask : ~0ull, acc, cnt);
         };
-        if (PIPE) {
+        {
             // two buffers, swapped by unrolling (no register copies); the
             // steady state issues unconditionally so that each combine waits
             // only for its own gathers
@@ -273,19 +272,12 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
             } else {
                 combine(P0, i);
             }
-        } else {
-#pragma unroll 1
-            for (int i = 0; i < n_sweeps; ++i) {
-                PlaneInFlight P;
-                issue_plane<Tap, G>(P, pc, cs, sn, sa, sb, ec);
-                rotate();
-                combine(P, i);
-            }
         }
         acc = wave_sum(acc);
         const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
         const float e = ec.inv_c > 0.0f ? d / (1.0f + d * ec.inv_c) : d;
         if (out_pair && lane == 0) out_pair[(int64_t)hyp * ec.n_pairs + p] = e;
+        if (out_count && lane == 0) out_count[(int64_t)hyp * ec.n_pairs + p] = cnt;
         wave_acc += (double)e;
     }
     if (Q == 1) {
@@ -305,16 +297,7 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
 // unused dynamic LDS allocation (160 KB per CU).  More resident waves than
 // this widen the set of pair tiles in flight per XCD beyond what its L2 can
 // hold, and L2 misses grow faster than latency hiding gains.
-static int blocks_per_cu_cap(int default_cap) {
-    static int env = [] {
-        const char *e = getenv("ECC_BLOCKS_PER_CU");
-        return e ? (atoi(e) < 0 ? 0 : atoi(e)) : -1;
-    }();
-    return env >= 0 ? env : default_cap;
-}
-
-size_t occupancy_lds_bytes(size_t static_bytes, int default_cap) {
-    const int cap = blocks_per_cu_cap(default_cap);
+size_t occupancy_lds_bytes(size_t static_bytes, int cap) {
     if (cap <= 0) return 0;
     size_t b = (160u * 1024u) / (size_t)cap;
     b = (b / 1024) * 1024;
@@ -322,49 +305,28 @@ size_t occupancy_lds_bytes(size_t static_bytes, int default_cap) {
     return b > static_bytes ? b - static_bytes : 0;
 }
 
-template <class Tap, class G, bool UNIFORM, bool PIPE>
-static hipError_t launch_fwd_v(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
-                               int n_tiles, hipStream_t s) {
+template <class Tap, class G>
+static hipError_t launch_fwd_t(const void *sino, const void *table, EvalConsts ec, float *out_pair,
+                               int32_t *out_count, double *partials, int n_tiles, hipStream_t s) {
     const int64_t total = plane_work_items(ec.B, n_tiles);
     const int64_t blocks = 8 * ((total + 7) / 8);
-    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G, UNIFORM, PIPE>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                       occupancy_lds_bytes(plane_kernel_lds<G>(), sizeof(Tap) == 8 ? kFwdBlocksPerCU32 : kFwdBlocksPerCU16),
-                       s, sino,
-                       (const PairConst<G> *)table, ec, out_pair, partials, n_tiles);
+    hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
+                       occupancy_lds_bytes(plane_kernel_lds<G>(),
+                                           sizeof(Tap) == 8 ? kFwdBlocksPerCU32 : kFwdBlocksPerCU16),
+                       s, sino, (const PairConst<G> *)table, ec, out_pair, out_count, partials, n_tiles);
     return hipGetLastError();
 }
 
-// Plane-loop variant: bit 1 (2) pair constants in scalar registers (else
-// LDS), bit 2 (4) two planes' gathers in flight; ECC_FWD_VARIANT overrides.
-static int fwd_variant() {
-    static int v = [] {
-        const char *e = getenv("ECC_FWD_VARIANT");
-        return e ? atoi(e) & 6 : kDefaultFwdVariant;
-    }();
-    return v;
-}
-
-template <class Tap, class G>
-static hipError_t launch_fwd_t(const void *sino, const void *table, EvalConsts ec, float *out_pair, double *partials,
-                               int n_tiles, hipStream_t s) {
-    switch (fwd_variant()) {
-        case 2: return launch_fwd_v<Tap, G, true, false>(sino, table, ec, out_pair, partials, n_tiles, s);
-        case 4: return launch_fwd_v<Tap, G, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
-        case 6: return launch_fwd_v<Tap, G, true, true>(sino, table, ec, out_pair, partials, n_tiles, s);
-        default: return launch_fwd_v<Tap, G, false, false>(sino, table, ec, out_pair, partials, n_tiles, s);
-    }
-}
-
 hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
-                          double *partials, int n_tiles, hipStream_t s) {
-    if (ec.geom64) {  // two planes' gathers in flight here too (1.5 % faster than one)
-        if (dtype == 0) return launch_fwd_v<TapF32, double, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
-        if (dtype == 1) return launch_fwd_v<TapBF16, double, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
-        return launch_fwd_v<TapF16, double, false, true>(sino, table, ec, out_pair, partials, n_tiles, s);
+                          int32_t *out_count, double *partials, int n_tiles, hipStream_t s) {
+    if (ec.geom64) {
+        if (dtype == 0) return launch_fwd_t<TapF32, double>(sino, table, ec, out_pair, out_count, partials, n_tiles, s);
+        if (dtype == 1) return launch_fwd_t<TapBF16, double>(sino, table, ec, out_pair, out_count, partials, n_tiles, s);
+        return launch_fwd_t<TapF16, double>(sino, table, ec, out_pair, out_count, partials, n_tiles, s);
     }
-    if (dtype == 0) return launch_fwd_t<TapF32, float>(sino, table, ec, out_pair, partials, n_tiles, s);
-    if (dtype == 1) return launch_fwd_t<TapBF16, float>(sino, table, ec, out_pair, partials, n_tiles, s);
-    return launch_fwd_t<TapF16, float>(sino, table, ec, out_pair, partials, n_tiles, s);
+    if (dtype == 0) return launch_fwd_t<TapF32, float>(sino, table, ec, out_pair, out_count, partials, n_tiles, s);
+    if (dtype == 1) return launch_fwd_t<TapBF16, float>(sino, table, ec, out_pair, out_count, partials, n_tiles, s);
+    return launch_fwd_t<TapF16, float>(sino, table, ec, out_pair, out_count, partials, n_tiles, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -95,8 +95,9 @@ size_t pair_const_bytes(bool geom64);
 // line route the method replaces)
 hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalConsts ec, void *table, hipStream_t s,
                              const double *pinv = nullptr);
+// out_pair [B][n_pairs] e and out_count [B][n_pairs] N_kappa, each optional
 hipError_t launch_ecc_fwd(const void *sino, const void *table, EvalConsts ec, int dtype, float *out_pair,
-                          double *partials, int n_tiles, hipStream_t s);
+                          int32_t *out_count, double *partials, int n_tiles, hipStream_t s);
 // adjoint: plane kernel -> per-pair sensitivities sens [B][n_pairs][13], then
 // per-pair tangent sweeps -> pair_grad [B][n_pairs][12]
 hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *vt, const ViewGeomGrad *vg,
@@ -133,10 +134,8 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kFwdBlocksPerCU32 = 3;
 constexpr int kFwdBlocksPerCU16 = 4;
 constexpr int kAdjBlocksPerCU = 4;
-// default plane-loop variant of the FP32 forward kernel (see ecc.hip)
-constexpr int kDefaultFwdVariant = 4;
-// dynamic LDS that, added to a kernel's static LDS, enforces the cap (the
-// environment variable ECC_BLOCKS_PER_CU overrides default_cap)
-size_t occupancy_lds_bytes(size_t static_bytes, int default_cap);
+// dynamic LDS that, added to a kernel's static LDS, caps resident
+// workgroups per CU at `cap` (0 = no cap)
+size_t occupancy_lds_bytes(size_t static_bytes, int cap);
 
 }  // namespace ecc

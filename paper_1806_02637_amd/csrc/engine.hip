@@ -127,6 +127,10 @@ Scan *find_scan(ecc_ctx *ctx, int32_t id) {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+// largest accepted distance (px) of a view's principal point from the
+// detector centre
+constexpr double kPrincipalTolPx = 1e-6;
+
 int n_tiles_for(int n_views) {
     const int nb = (n_views + 7) / 8;  // 8-view blocks, tiles = block pairs I <= J
     return nb * (nb + 1) / 2;
@@ -292,6 +296,13 @@ ecc_status ecc_scan_load(ecc_ctx *ctx, int32_t *scan_id, int32_t n_views, int32_
         for (int i = 0; i < 3; ++i)
             if (!isfinite(intr[3 * v + i])) return fail(ECC_E_ARG, "non-finite intrinsics (view %d)", v);
         if (!(intr[3 * v] > 0.0)) return fail(ECC_E_ARG, "focal length must be positive (view %d)", v);
+        // the hit test of Eq. 15 and the sinogram's t range are centred on
+        // the principal point, so it must be the detector centre
+        if (fabs(intr[3 * v + 1] - 0.5 * (W - 1)) > kPrincipalTolPx || fabs(intr[3 * v + 2] - 0.5 * (H - 1)) > kPrincipalTolPx)
+            return fail(ECC_E_ARG,
+                        "principal point (%.6f, %.6f) of view %d is not the detector centre ((W-1)/2, (H-1)/2) = "
+                        "(%.6f, %.6f)",
+                        intr[3 * v + 1], intr[3 * v + 2], v, 0.5 * (W - 1), 0.5 * (H - 1));
         const double det = p[0] * (p[5] * p[10] - p[6] * p[9]) - p[1] * (p[4] * p[10] - p[6] * p[8]) +
                            p[2] * (p[4] * p[9] - p[5] * p[8]);
         const int sg = det > 0 ? 1 : (det < 0 ? -1 : 0);
@@ -648,26 +659,36 @@ ecc_status ecc_workspace_bytes(ecc_ctx *ctx, int32_t scan_id, int32_t B, int32_t
 
 static ecc_status cost_impl(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
                             const double *pinv_dev, const ecc_eval_params *params, double *out_cost_dev,
-                            float *out_pair_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream);
+                            float *out_pair_dev, int32_t *out_count_dev, void *workspace_dev,
+                            uint64_t workspace_bytes, void *stream);
 
 ecc_status ecc_cost(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev, const ecc_eval_params *params,
                     double *out_cost_dev, float *out_pair_dev, void *workspace_dev, uint64_t workspace_bytes,
                     void *stream) {
-    return cost_impl(ctx, scan_id, B, theta_dev, nullptr, params, out_cost_dev, out_pair_dev, workspace_dev,
-                     workspace_bytes, stream);
+    return cost_impl(ctx, scan_id, B, theta_dev, nullptr, params, out_cost_dev, out_pair_dev, nullptr,
+                     workspace_dev, workspace_bytes, stream);
+}
+
+ecc_status ecc_cost_counts(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
+                           const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
+                           int32_t *out_count_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream) {
+    if (!out_count_dev) return fail(ECC_E_ARG, "null count pointer");
+    return cost_impl(ctx, scan_id, B, theta_dev, nullptr, params, out_cost_dev, out_pair_dev, out_count_dev,
+                     workspace_dev, workspace_bytes, stream);
 }
 
 ecc_status ecc_cost_pinv(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev, const double *pinv_dev,
                          const ecc_eval_params *params, double *out_cost_dev, float *out_pair_dev,
                          void *workspace_dev, uint64_t workspace_bytes, void *stream) {
     if (!pinv_dev) return fail(ECC_E_ARG, "null pseudo-inverse pointer");
-    return cost_impl(ctx, scan_id, B, theta_dev, pinv_dev, params, out_cost_dev, out_pair_dev, workspace_dev,
-                     workspace_bytes, stream);
+    return cost_impl(ctx, scan_id, B, theta_dev, pinv_dev, params, out_cost_dev, out_pair_dev, nullptr,
+                     workspace_dev, workspace_bytes, stream);
 }
 
 static ecc_status cost_impl(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double *theta_dev,
                             const double *pinv_dev, const ecc_eval_params *params, double *out_cost_dev,
-                            float *out_pair_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream) {
+                            float *out_pair_dev, int32_t *out_count_dev, void *workspace_dev,
+                            uint64_t workspace_bytes, void *stream) {
     if (!ctx) return fail(ECC_E_ARG, "null context");
     // the lock spans the (asynchronous) launches so that a concurrent
     // ecc_scan_free cannot release the scan between check and launch
@@ -690,7 +711,8 @@ static ecc_status cost_impl(ecc_ctx *ctx, int32_t scan_id, int32_t B, const doub
     void *table = ws + w.table_off;
     HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, nullptr, hs));
     HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs, pinv_dev));
-    HIP_TRY(launch_ecc_fwd(s->sino_dev, table, ec, s->layout.dtype, out_pair_dev, partials, n_tiles, hs));
+    HIP_TRY(launch_ecc_fwd(s->sino_dev, table, ec, s->layout.dtype, out_pair_dev, out_count_dev, partials, n_tiles,
+                           hs));
     HIP_TRY(launch_reduce_cost(partials, n_tiles, B, out_cost_dev, hs));
     return ok();
 }
@@ -720,7 +742,7 @@ ecc_status ecc_cost_noalloc(ecc_ctx *ctx, int32_t scan_id, int32_t B, const doub
     // the scan may change between the size check and the evaluation only by
     // ecc_scan_free, which cost_impl reports as ECC_E_NOSCAN; it checks the
     // size again against the scratch it is given
-    return cost_impl(ctx, scan_id, B, theta_dev, nullptr, params, out_cost_dev, out_pair_dev, ptr,
+    return cost_impl(ctx, scan_id, B, theta_dev, nullptr, params, out_cost_dev, out_pair_dev, nullptr, ptr,
                      kNoAllocScratchBytes, stream);
 }
 

@@ -127,17 +127,28 @@ class Scan:
         return th.to(self.engine.device).contiguous()
 
     def cost(self, theta, K: int, R_mm: float, c: float = math.inf, geom: str = "f32", with_pairs: bool = False,
-             workspace: torch.Tensor | None = None, kappa: str = "object"):
-        """Returns cost [B] (FP64 device tensor) and, with_pairs, e [B, n_pairs]."""
+             workspace: torch.Tensor | None = None, kappa: str = "object", with_counts: bool = False):
+        """Returns cost [B] (FP64 device tensor), then e [B, n_pairs] if
+        with_pairs and the plane counts N_kappa [B, n_pairs] (int32) if
+        with_counts."""
         th = self._theta(theta)
         Bn = th.shape[0]
-        out = torch.empty(Bn, dtype=torch.float64, device=self.engine.device)
-        pairs = torch.empty((Bn, self.n_pairs), dtype=torch.float32, device=self.engine.device) if with_pairs else None
+        dev = self.engine.device
+        out = torch.empty(Bn, dtype=torch.float64, device=dev)
+        pairs = torch.empty((Bn, self.n_pairs), dtype=torch.float32, device=dev) if with_pairs else None
         ws = self.workspace(Bn, False) if workspace is None else workspace
-        B.ecc_cost(self.ctx, self.id, Bn, th.data_ptr(), self.params(K, R_mm, c, geom, kappa), out.data_ptr(),
-                   pairs.data_ptr() if pairs is not None else 0, ws.data_ptr(), ws.numel(),
-                   _stream_handle(self.engine.device))
-        return (out, pairs) if with_pairs else out
+        prm = self.params(K, R_mm, c, geom, kappa)
+        pp = pairs.data_ptr() if pairs is not None else 0
+        counts = None
+        if with_counts:
+            counts = torch.empty((Bn, self.n_pairs), dtype=torch.int32, device=dev)
+            B.ecc_cost_counts(self.ctx, self.id, Bn, th.data_ptr(), prm, out.data_ptr(), pp, counts.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream_handle(dev))
+        else:
+            B.ecc_cost(self.ctx, self.id, Bn, th.data_ptr(), prm, out.data_ptr(), pp, ws.data_ptr(), ws.numel(),
+                       _stream_handle(dev))
+        res = (out,) + ((pairs,) if with_pairs else ()) + ((counts,) if with_counts else ())
+        return res if len(res) > 1 else out
 
     def fdk(self, images, vol, theta=None) -> torch.Tensor:
         """FDK reconstruction [nz, ny, nx] (FP32 device tensor) of this scan's

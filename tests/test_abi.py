@@ -12,8 +12,8 @@ from paper_1806_02637_amd import binding
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_functions():
-    with open(os.path.join(ROOT, "include", "ecc.h")) as fh:
+def _declared_functions(header="ecc.h"):
+    with open(os.path.join(ROOT, "include", header)) as fh:
         text = fh.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(ecc_[a-z_]+)\s*\(", text)))
@@ -23,13 +23,14 @@ def test_header_and_binding_agree():
     declared = _declared_functions()
     assert declared, "no declarations parsed"
     assert sorted(binding.SYMBOLS) == declared
+    assert sorted(binding.PROBE_SYMBOLS) == _declared_functions("ecc_probe.h")
 
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(binding.LIB_PATH):
         pytest.fail("libecc.so is not built; run __graft_entry__.build()")
     lib = ctypes.CDLL(binding.LIB_PATH)
-    for name in _declared_functions():
+    for name in _declared_functions() + _declared_functions("ecc_probe.h"):
         assert hasattr(lib, name), name
 
 

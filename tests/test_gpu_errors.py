@@ -69,6 +69,14 @@ def test_argument_and_state_errors(scan_inputs):
         st, _ = _status(B.ecc_scan_load, ctx, g.n_views, g.W, g.H, Pnan.ctypes.data, intr.ctypes.data,
                         imgs.ctypes.data, 0)
         assert st == B.ECC_E_ARG
+        # a principal point off the detector centre (the hit test and the
+        # sinogram's t range are centred on it): refused, with the reason
+        for col, shift in ((1, 0.5), (2, -3.0)):
+            ioff = intr.copy()
+            ioff[5, col] += shift
+            st, msg = _status(B.ecc_scan_load, ctx, g.n_views, g.W, g.H, P.ctypes.data, ioff.ctypes.data,
+                              imgs.ctypes.data, 0)
+            assert st == B.ECC_E_ARG and "principal point" in msg, msg
         sid = B.ecc_scan_load(ctx, g.n_views, g.W, g.H, P.ctypes.data, intr.ctypes.data, imgs.ctypes.data, 0)
         th = torch.zeros((2, g.n_views, 6), dtype=torch.float64, device="cuda")
         out = torch.empty(2, dtype=torch.float64, device="cuda")
