@@ -1,0 +1,233 @@
+"""Writes the oracle's full-size golden records (FP64, oracle only):
+
+* ``mid248_h0.txt.gz`` -- the 248-view workload (620x480 at 0.616 mm,
+  360x512 sinogram, K = 256, object-sphere range) under its motion
+  hypothesis 0 (seed 1002, the first of the batch of 32 the benchmark draws):
+  every one of its 30,628 pairs, in row-major triangle order.
+* ``full496_sample.txt`` -- the 496-view workload (1240x960 at 0.308 mm,
+  768x1024 sinogram, K = 512) on 72 pairs -- adjacent views (the shortest
+  baselines), views 179.8 to 180.2 degrees apart (baselines close to the
+  isocentre), mid-range and 54 seeded random pairs -- under hypotheses 0, 7,
+  19 and 31 of the benchmark's batch of 32 (seed 1003) and one large-motion
+  hypothesis (seed 1103, rotations N(0, 3 deg), translations N(0, 20 mm)),
+  under which about half the pairs have planes that miss a detector
+  (N_kappa < K).
+
+Each row holds, per pair: e (Eqs. 15-16 with c = inf, so e = d), N_kappa
+(the planes whose lines hit both detectors) and the pair's scale
+(1/2) mean over those planes of (S_a^2 + S_b^2), against which per-pair
+differences are measured (e itself tends to 0 on consistent data).  The
+images come from the seeded input generator; every value from ``oracle``.
+
+The oracle's own ``lookup`` runs three times per pair: first on a stand-in
+sinogram that records which cells each view needs, then (after those cells
+are computed once per view with ``oracle.sinogram.drho_cells``) on the
+filled cells to produce the values.
+
+Usage: python tests/golden/make_full.py [mid248|full496] [--workers 8]
+"""
+from __future__ import annotations
+
+import argparse
+import gzip
+import multiprocessing as mp
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from oracle.ecc import as_rows, inconsistency, lookup, pair_geometry, robust  # noqa: E402
+from oracle.sinogram import cosine_weighted, drho_cells  # noqa: E402
+from paper_1806_02637_amd import inputs  # noqa: E402
+
+LARGE_MOTION = dict(seed=1103, rot_sd_deg=3.0, trans_sd_mm=20.0)
+FULL_HYPS = (0, 7, 19, 31)
+
+
+def full496_pairs():
+    n = 496
+    fixed = [(0, 1), (123, 124), (247, 248), (370, 371), (494, 495), (200, 202),
+             (0, 445), (0, 446), (24, 470), (49, 495), (50, 495), (10, 456),
+             (0, 248), (100, 300), (248, 400), (300, 495), (0, 100), (400, 450)]
+    rng = np.random.default_rng(496)
+    out = list(fixed)
+    while len(out) < 72:
+        a, b = sorted(int(x) for x in rng.choice(n, 2, replace=False))
+        if (a, b) not in out:
+            out.append((a, b))
+    return out
+
+
+class _Recorder:
+    """Sinogram stand-in: records the cells asked for, returns zeros."""
+
+    def __init__(self):
+        self.cells_seen = {}
+
+    def cells(self, view, m, k):
+        key = np.asarray(m, dtype=np.int64) * 65536 + np.asarray(k, dtype=np.int64)
+        self.cells_seen.setdefault(view, set()).update(key.ravel().tolist())
+        return np.zeros(np.shape(m))
+
+
+class _Filled:
+    """Sinogram whose needed cells were computed beforehand (NaN elsewhere)."""
+
+    def __init__(self, data, slot):
+        self.data, self.slot = data, slot
+
+    def cells(self, view, m, k):
+        v = self.data[self.slot[view]][m, k]
+        assert not np.isnan(v).any(), f"cell of view {view} was not computed"
+        return v
+
+
+_G = {}
+
+
+def _init(state):
+    _G.update(state)
+    if "data_path" in state:
+        _G["data"] = np.load(state["data_path"], mmap_mode="r")
+    if "img_path" in state:
+        _G["images"] = np.load(state["img_path"], mmap_mode="r")
+
+
+def _eval_chunk(args):
+    """(hyp label, a, b) items -> recorded cells or (e, N, scale) rows."""
+    items, mode = args
+    P, intr, grid, params, thetas = _G["P"], _G["intr"], _G["grid"], _G["params"], _G["thetas"]
+    sino = _Recorder() if mode == "record" else _Filled(_G["data"], _G["slot"])
+    rows = []
+    for h, a, b in items:
+        th = thetas[h]
+        geo = pair_geometry(as_rows(P[a]), as_rows(P[b]), list(th[a]), list(th[b]), params)
+        S_a, hit_a = lookup(geo["l_a"], intr[a], grid, sino, a)
+        S_b, hit_b = lookup(geo["l_b"], intr[b], grid, sino, b)
+        if mode == "record":
+            continue
+        hit = hit_a & hit_b
+        d, N = inconsistency(S_a, S_b, hit)
+        e = robust(d, params.c)
+        scale = 0.5 * float(np.mean((S_a ** 2 + S_b ** 2)[hit])) if N else 0.0
+        rows.append((h, a, b, float(e), int(N), scale))
+    return sino.cells_seen if mode == "record" else rows
+
+
+def _cells_of_view(args):
+    slot, view, flat = args
+    grid, intr = _G["grid"], _G["intr"]
+    f, u0, v0 = intr[view]
+    gw = cosine_weighted(_G["images"][slot], f, u0, v0)
+    m, k = flat // 65536, flat % 65536
+    return slot, m, k, drho_cells(gw, grid, u0, v0, m, k)
+
+
+def generate(name, items, thetas, workers, tmp):
+    w = inputs.WORKLOADS[name]
+    g = w.geom
+    P, intr = g.projection_matrices(), g.intrinsics()
+    grid = oracle.SinoGrid(g.W, g.H, w.n_alpha, w.n_t, w.ds_px)
+    params = oracle.EccParams(w.K, w.R_mm)
+    state = dict(P=P, intr=intr, grid=grid, params=params, thetas=thetas)
+    ctx = mp.get_context("spawn")
+    chunks = [items[i::workers * 8] for i in range(workers * 8)]
+    t0 = time.time()
+    with ctx.Pool(workers, _init, (state,)) as pool:
+        seen = {}
+        for part in pool.imap_unordered(_eval_chunk, [(c, "record") for c in chunks]):
+            for v, s in part.items():
+                seen.setdefault(v, set()).update(s)
+    views = sorted(seen)
+    print(f"{name}: {len(items)} pair evaluations touch {sum(len(s) for s in seen.values())} cells of "
+          f"{len(views)} views ({time.time() - t0:.0f} s)", flush=True)
+    t0 = time.time()
+    imgs = inputs.project(g, w.phantom(), views=views)
+    img_path = os.path.join(tmp, "images.npy")
+    np.save(img_path, imgs)
+    del imgs
+    print(f"{name}: projected {len(views)} views ({time.time() - t0:.0f} s)", flush=True)
+    t0 = time.time()
+    slot = {v: i for i, v in enumerate(views)}
+    data = np.full((len(views), w.n_alpha + 1, w.n_t), np.nan)
+    tasks = []
+    for v in views:
+        flat = np.array(sorted(seen[v]), dtype=np.int64)
+        for i in range(0, len(flat), 4000):
+            tasks.append((slot[v], v, flat[i:i + 4000]))
+    with ctx.Pool(workers, _init, (dict(state, img_path=img_path),)) as pool:
+        for s, m, k, vals in pool.imap_unordered(_cells_of_view, tasks, chunksize=4):
+            data[s][m, k] = vals
+    data_path = os.path.join(tmp, "cells.npy")
+    np.save(data_path, data)
+    del data
+    print(f"{name}: computed the cells ({time.time() - t0:.0f} s)", flush=True)
+    t0 = time.time()
+    with ctx.Pool(workers, _init, (dict(state, data_path=data_path, slot=slot),)) as pool:
+        rows = [r for part in pool.imap_unordered(_eval_chunk, [(c, "eval") for c in chunks]) for r in part]
+    print(f"{name}: evaluated ({time.time() - t0:.0f} s)", flush=True)
+    order = {it: i for i, it in enumerate(items)}
+    rows.sort(key=lambda r: order[r[:3]])
+    return w, rows
+
+
+def _header(w, lines):
+    g = w.geom
+    return [f"# oracle golden record: {w.name}, {g.n_views} views, {g.W}x{g.H} at {g.pitch_mm} mm, "
+            f"sinogram {w.n_alpha}x{w.n_t}, ds = {w.ds_px} px, K = {w.K}, R = {w.R_mm!r} mm, c = inf, "
+            f"object-sphere range, phantom seed {w.phantom_seed} ({w.n_ellipsoids} ellipsoids)"] + \
+           [f"# {x}" for x in lines] + \
+           ["# written by tests/golden/make_full.py from oracle/ only (Eqs. 13-17 per pair)",
+            "# columns: hypothesis a b e N_kappa scale=(1/2)mean(S_a^2+S_b^2)"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", nargs="*", default=["mid248", "full496"])
+    ap.add_argument("--workers", type=int, default=8)
+    args = ap.parse_args()
+    with tempfile.TemporaryDirectory() as tmp:
+        if "mid248" in args.which:
+            w = inputs.WORKLOADS["mid248"]
+            n = w.geom.n_views
+            thetas = {"h0": w.motion(1)[0]}
+            items = [("h0", a, b) for a in range(n) for b in range(a + 1, n)]
+            w, rows = generate("mid248", items, thetas, args.workers, tmp)
+            total = sum(r[3] for r in rows)
+            lines = _header(w, [f"hypothesis h0 = hypothesis 0 of random_motion({w.motion_seed}, B, {n}) "
+                                f"(rotations N(0, 0.5 deg), translations N(0, 1 mm))",
+                                f"total cost of h0 (sum of e over all {len(rows)} pairs): {total!r}"])
+            with gzip.open(os.path.join(HERE, "mid248_h0.txt.gz"), "wt") as fh:
+                fh.write("\n".join(lines) + "\n")
+                for h, a, b, e, N, s in rows:
+                    fh.write(f"{h} {a} {b} {e:.12e} {N} {s:.6e}\n")
+        if "full496" in args.which:
+            w = inputs.WORKLOADS["full496"]
+            n = w.geom.n_views
+            bench = w.motion(32)
+            thetas = {f"h{i}": bench[i] for i in FULL_HYPS}
+            thetas["large"] = inputs.random_motion(LARGE_MOTION["seed"], 1, n, LARGE_MOTION["rot_sd_deg"],
+                                                   LARGE_MOTION["trans_sd_mm"])[0]
+            pairs = full496_pairs()
+            items = [(h, a, b) for h in thetas for a, b in pairs]
+            w, rows = generate("full496", items, thetas, args.workers, tmp)
+            lines = _header(w, [f"hypotheses h0 h7 h19 h31 = those of random_motion({w.motion_seed}, 32, {n}) "
+                                f"(the benchmark's batch)",
+                                f"hypothesis large = random_motion({LARGE_MOTION['seed']}, 1, {n}, "
+                                f"{LARGE_MOTION['rot_sd_deg']}, {LARGE_MOTION['trans_sd_mm']})[0]"])
+            with open(os.path.join(HERE, "full496_sample.txt"), "w") as fh:
+                fh.write("\n".join(lines) + "\n")
+                for h, a, b, e, N, s in rows:
+                    fh.write(f"{h} {a} {b} {e:.12e} {N} {s:.6e}\n")
+
+
+if __name__ == "__main__":
+    main()
