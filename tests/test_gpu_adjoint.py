@@ -27,6 +27,22 @@ def _say(*a):
     print(*a, flush=True)
 
 
+def _elementwise(got, ref, rtol, atol_frac, label):
+    """Every component: |got - ref| <= rtol |ref| + atol_frac * max |ref|
+    (the max over the vector the components belong to, the last axis of a
+    per-pair array).  Returns the worst ratio of error to allowance; a
+    component whose sign is flipped fails unless it is below about
+    atol_frac / 2 of the largest one."""
+    got, ref = np.asarray(got, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    scale = np.abs(ref).max(axis=-1, keepdims=True) if ref.ndim > 1 else np.abs(ref).max()
+    allow = rtol * np.abs(ref) + atol_frac * scale + 1e-300
+    ratio = np.abs(got - ref) / allow
+    worst = float(ratio.max())
+    _say(f"  {label}: element-wise worst error / allowance {worst:.3f} (rtol {rtol:g}, atol {atol_frac:g} max)")
+    assert worst <= 1.0, (label, np.unravel_index(int(np.argmax(ratio)), ratio.shape))
+    return worst
+
+
 @pytest.fixture(scope="module")
 def eng():
     import torch
@@ -59,6 +75,9 @@ def test_gradient_matches_oracle_small16(eng, small16):
             err = np.linalg.norm(grad[h] - g_ref) / np.linalg.norm(g_ref)
             _say(f"  c={c} hyp {h}: grad rel L2 {err:.2e}")
             assert err <= 2e-4
+            # each of the 6N components, and each pair's 12 components
+            _elementwise(grad[h].ravel(), g_ref.ravel(), 1e-3, 1e-4, f"c={c} hyp {h} per view")
+            _elementwise(pg[h], pg_ref, 1e-2, 1e-3, f"c={c} hyp {h} per pair")
             nrm = np.linalg.norm(pg_ref, axis=1) + 1e-30
             perr = np.linalg.norm(pg[h] - pg_ref, axis=1) / nrm
             assert np.quantile(perr, 0.99) <= 1e-3 and perr.max() <= 1e-2, perr.max()
@@ -112,6 +131,7 @@ def test_gradient_sampled_pairs_and_fd_adj248(eng):
         got = pg[pair_index(a, b, g.n_views)]
         err = np.linalg.norm(got - gref) / (np.linalg.norm(gref) + 1e-30)
         assert err <= 2e-3, (a, b, err)
+        _elementwise(got, gref, 1e-2, 2e-3, f"adj248 pair ({a}, {b})")
     # central differences of the GPU cost, h = 1e-3 deg / mm
     h = 1e-3
     idx = [(v, q) for v in rng.choice(g.n_views, 6, replace=False).tolist() for q in range(6)]
@@ -183,4 +203,6 @@ def test_gradient_precision_forms_small16(eng, small16, dtype, geom):
         err = np.linalg.norm(grad[h] - g_ref) / np.linalg.norm(g_ref)
         _say(f"  hyp {h}: cost {float(cost[h]):.6e} vs {c_ref:.6e}, grad rel L2 {err:.2e}")
         assert err <= bar
+        _elementwise(grad[h].ravel(), g_ref.ravel(), 1e-3 if geom == "f64" else 1e-2,
+                     1e-4 if geom == "f64" else 1e-3, f"{dtype}/{geom} hyp {h} per view")
     scan.free()
