@@ -17,12 +17,10 @@ import pytest
 
 import oracle
 from oracle.ecc import as_rows, lookup, pair_geometry, pair_index, pair_list
+from precision_model import U, model_bound as _model_bound
 from paper_1806_02637_amd import inputs
 
 pytestmark = pytest.mark.gpu
-
-U = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
-
 
 def _say(*a):
     print(*a, flush=True)
@@ -38,26 +36,6 @@ def eng():
     e = engine.Engine(0)
     yield e
     e.close()
-
-
-def _model_bound(P, intr, theta, grid, sino, params, u, pairs=None):
-    """Per-hypothesis relative error bound of the storage-rounding model."""
-    bias = 0.0
-    noise2 = 0.0
-    total = 0.0
-    for a, b in pairs or pair_list(len(P)):
-        g = pair_geometry(as_rows(P[a]), as_rows(P[b]), list(theta[a]), list(theta[b]), params)
-        Sa, ha = lookup(g["l_a"], intr[a], grid, sino, a)
-        Sb, hb = lookup(g["l_b"], intr[b], grid, sino, b)
-        h = ha & hb
-        if not h.any():
-            continue
-        ms = np.mean(0.5 * (Sa[h] ** 2 + Sb[h] ** 2))
-        d = np.mean((Sa[h] - Sb[h]) ** 2)
-        total += d
-        bias += (2 * u * u / 3) * ms
-        noise2 += (2 * u) ** 2 * d * ms / h.sum()
-    return (bias + math.sqrt(noise2)) / total
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])

@@ -208,3 +208,51 @@ def test_detector_range_requests(served):
             c0 = sc.cost(th, K, R, kappa=kappa)
         assert np.array_equal(r.cost, c0.cpu().numpy())
     srv.close()
+
+
+def test_served_bf16_results_against_oracle(small16):
+    """Ten requests of two hypotheses each (half cost + gradient) served
+    together from BF16 sinograms of the 16-view scan, every served cost
+    against the FP64 oracle: on the stored (decoded BF16) sinograms to the
+    FP32 bar 1e-5, and on the oracle's own FP64 sinograms within the stated
+    BF16 bound (4x the storage-rounding model plus 1e-5)."""
+    import torch
+
+    from paper_1806_02637_amd import engine
+    from paper_1806_02637_amd.serve import Server
+
+    import oracle
+    from precision_model import U, model_bound
+
+    _say("case: served BF16 against the oracle")
+    s = small16
+    g = s["geom"]
+    eng = engine.Engine(0)
+    scan = eng.load_scan(s["P"], s["intr"], s["images"])
+    scan.build_sinograms(s["w"].n_alpha, s["w"].n_t, s["w"].ds_px, "bf16")
+    stored = oracle.FullSinograms(np.stack([scan.read_sinogram(v) for v in range(g.n_views)]).astype(np.float64),
+                                  s["grid"])
+    params = s["params"]
+    srv = Server(eng, n_slots=4, arena_bytes=256 << 20)
+    thetas = [inputs.random_motion(300 + i, 2, g.n_views) for i in range(10)]
+    ids = [srv.submit(scan, th, params.K, params.R_mm, with_grad=bool(i % 2)) for i, th in enumerate(thetas)]
+    results = [srv.wait(i) for i in ids]
+    srv.close()
+    assert len({r.slot for r in results}) >= 2
+    checked = 0
+    for th, r in zip(thetas, results):
+        for h in range(2):
+            c_st = oracle.ecc_cost(s["P"], s["intr"], th[h], s["grid"], stored, params)[0]
+            c64 = oracle.ecc_cost(s["P"], s["intr"], th[h], s["grid"], s["sino"], params)[0]
+            bound = 4 * model_bound(s["P"], s["intr"], th[h], s["grid"], s["sino"], params, U["bf16"]) + 1e-5
+            rel_st = abs(r.cost[h] - c_st) / c_st
+            rel64 = abs(r.cost[h] - c64) / c64
+            _say(f"  request {r.request_id} hyp {h} (slot {r.slot}): vs stored {rel_st:.1e}, "
+                 f"vs FP64 {rel64:.1e} (BF16 bound {bound:.1e})")
+            assert rel_st <= 1e-5
+            assert rel64 <= bound
+            checked += 1
+    assert checked >= 8
+    scan.free()
+    eng.close()
+    torch.cuda.synchronize()
