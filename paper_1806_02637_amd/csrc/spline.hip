@@ -18,12 +18,16 @@ namespace {
 __device__ __forceinline__ double s_abs(double x) { return fabs(x); }
 __device__ __forceinline__ Dual s_abs(Dual x) { return x.v < 0.0 ? -x : x; }
 
+// Node values are read through an accessor y(i) (a node value, or a dual
+// number carrying d/d node j) rather than a per-thread array: an Akima value
+// needs only the six nodes around its segment.
+
 // Segment slope m_k for k in [-2, n]: interior slopes from the nodes, two
 // linearly extrapolated slopes beyond each end.
-template <class T>
-__device__ T seg_slope(const SplineKnots &kn, const T *y, int k) {
+template <class T, class Y>
+__device__ T seg_slope(const SplineKnots &kn, const Y &y, int k) {
     const int n = kn.n;
-    auto m = [&](int i) { return (y[i + 1] - y[i]) / T(kn.x[i + 1] - kn.x[i]); };
+    auto m = [&](int i) { return (y(i + 1) - y(i)) / T(kn.x[i + 1] - kn.x[i]); };
     if (k >= 0 && k <= n - 2) return m(k);
     if (k == -1) return T(2.0) * m(0) - m(1);
     if (k == -2) return T(3.0) * m(0) - T(2.0) * m(1);  // 2 m_{-1} - m_0
@@ -32,10 +36,10 @@ __device__ T seg_slope(const SplineKnots &kn, const T *y, int k) {
 }
 
 // Akima's derivative estimate at node i.
-template <class T>
-__device__ T node_slope(const SplineKnots &kn, const T *y, int i) {
-    const T m_2 = seg_slope(kn, y, i - 2), m_1 = seg_slope(kn, y, i - 1);
-    const T m0 = seg_slope(kn, y, i), m1 = seg_slope(kn, y, i + 1);
+template <class T, class Y>
+__device__ T node_slope(const SplineKnots &kn, const Y &y, int i) {
+    const T m_2 = seg_slope<T>(kn, y, i - 2), m_1 = seg_slope<T>(kn, y, i - 1);
+    const T m0 = seg_slope<T>(kn, y, i), m1 = seg_slope<T>(kn, y, i + 1);
     const T w_hi = s_abs(m1 - m0), w_lo = s_abs(m_1 - m_2);
     if (g_val(w_hi) + g_val(w_lo) == 0.0) return T(0.5) * (m_1 + m0);
     return (w_hi * m_1 + w_lo * m0) / (w_hi + w_lo);
@@ -48,13 +52,13 @@ __device__ int segment_of(const SplineKnots &kn, double x) {
 }
 
 // The interpolant at x (inside [x_0, x_{n-1}]).
-template <class T>
-__device__ T akima_at(const SplineKnots &kn, const T *y, double x) {
+template <class T, class Y>
+__device__ T akima_at(const SplineKnots &kn, const Y &y, double x) {
     const int i = segment_of(kn, x);
     const double h = kn.x[i + 1] - kn.x[i];
     const double s = (x - kn.x[i]) / h, s2 = s * s, s3 = s2 * s;
-    const T ti = node_slope(kn, y, i), ti1 = node_slope(kn, y, i + 1);
-    return T(2 * s3 - 3 * s2 + 1) * y[i] + T((s3 - 2 * s2 + s) * h) * ti + T(-2 * s3 + 3 * s2) * y[i + 1] +
+    const T ti = node_slope<T>(kn, y, i), ti1 = node_slope<T>(kn, y, i + 1);
+    return T(2 * s3 - 3 * s2 + 1) * y(i) + T((s3 - 2 * s2 + s) * h) * ti + T(-2 * s3 + 3 * s2) * y(i + 1) +
            T((s3 - s2) * h) * ti1;
 }
 
@@ -67,9 +71,9 @@ __global__ __launch_bounds__(256) void spline_motion_kernel(SplineKnots kn, int 
     const int c = (int)(idx % 6);
     const int64_t bl = idx / 6;
     const int lam = (int)(bl % n_views), b = (int)(bl / n_views);
-    double y[kMaxSplineNodes];
-    for (int j = 0; j < kn.n; ++j) y[j] = nodes[((int64_t)b * 6 + c) * kn.n + j];
-    theta[idx] = akima_at(kn, y, (double)lam);
+    const double *yb = nodes + ((int64_t)b * 6 + c) * kn.n;
+    auto y = [yb](int i) { return yb[i]; };
+    theta[idx] = akima_at<double>(kn, y, (double)lam);
 }
 
 // workgroup = (hypothesis, parameter, node): sum over the views the node
@@ -84,15 +88,15 @@ __global__ __launch_bounds__(256) void spline_grad_kernel(SplineKnots kn, int B,
     const int j = (int)(idx % kn.n);
     const int64_t bc = idx / kn.n;
     const int c = (int)(bc % 6), b = (int)(bc / 6);
-    Dual y[kMaxSplineNodes];
-    for (int i = 0; i < kn.n; ++i) y[i] = Dual(nodes[bc * kn.n + i], i == j ? 1.0 : 0.0);
+    const double *yb = nodes + bc * kn.n;
+    auto y = [yb, j](int i) { return Dual(yb[i], i == j ? 1.0 : 0.0); };
     const double x_lo = kn.x[j >= 3 ? j - 3 : 0], x_hi = kn.x[j + 3 <= kn.n - 1 ? j + 3 : kn.n - 1];
     int l0 = (int)ceil(x_lo), l1 = (int)floor(x_hi);
     if (l0 < 0) l0 = 0;
     if (l1 > n_views - 1) l1 = n_views - 1;
     double acc = 0.0;
     for (int lam = l0 + (int)threadIdx.x; lam <= l1; lam += blockDim.x)
-        acc += (double)grad_theta[((int64_t)b * n_views + lam) * 6 + c] * akima_at(kn, y, (double)lam).d;
+        acc += (double)grad_theta[((int64_t)b * n_views + lam) * 6 + c] * akima_at<Dual>(kn, y, (double)lam).d;
     __shared__ double red[256];
     red[threadIdx.x] = acc;
     __syncthreads();
