@@ -405,68 +405,169 @@ def measure_fdk(scan, imgs, reps=3):
             "filter of every detector row, back-projection"}
 
 
-def measure_serving(eng, n_requests=48, seed=7, load=0.8):
+GATHER_LEVELS = (("l2", 2 << 20), ("mall", 128 << 20), ("hbm", 4 << 30))
+
+
+def measure_gather_peaks(iters=1024, n_blocks=4096, reps=5):
+    """Measured peaks of 16-byte gathers (ecc_probe_gather) from a buffer
+    that lives in one level: 2 MiB (within one XCD's 4 MB L2), 128 MiB
+    (within the 256 MB Infinity Cache), 4 GiB (HBM).  Pattern "random": each
+    lane its own random element (a wavefront's loads touch 64 lines, as the
+    forward kernel's taps do where lanes' lines differ); "coherent": each
+    wavefront one random 1 KiB block.  Gathered bytes / launch time, median
+    of `reps` launches timed with events on the stream the probe runs on."""
+    import torch
+
+    from paper_1806_02637_amd import binding as Bnd
+
+    out = {}
+    dev_out = torch.empty(n_blocks * 256, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    gathered = 16.0 * iters * 256 * n_blocks
+    for name, nbytes in GATHER_LEVELS:
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        for pattern, pname in ((0, "random"), (1, "coherent")):
+            for _ in range(2):
+                Bnd.ecc_probe_gather(buf.data_ptr(), nbytes, pattern, iters, n_blocks, dev_out.data_ptr(),
+                                     stream.cuda_stream)
+            ms = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                Bnd.ecc_probe_gather(buf.data_ptr(), nbytes, pattern, iters, n_blocks, dev_out.data_ptr(),
+                                     stream.cuda_stream)
+                e1.record(stream)
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            m = float(np.median(ms))
+            out[f"{name}_{pname}_gbs"] = gathered / (m * 1e-3) / 1e9
+        del buf
+    torch.cuda.empty_cache()
+    out.update(buffer_bytes={n: b for n, b in GATHER_LEVELS}, gathered_bytes_per_launch=gathered,
+               note="16-byte loads, 4 in flight per lane, 4096 x 256 threads")
+    return out
+
+
+SERVE_LEGS = (("serial_f32", "f32", 1), ("serial_bf16", "bf16", 1), ("served_f32", "f32", 4),
+              ("served_bf16", "bf16", 4))
+
+
+def measure_serving(eng, n_requests=200, seed=7, loads=(0.5, 0.8, 0.95), legs=SERVE_LEGS):
     """Served form: 8 resident scans of uneven view counts, Poisson arrivals of
-    64-hypothesis requests (half cost+gradient).  The same trace is served (a)
-    with BF16 sinograms by the continuous-batching server (4 slots, work in
-    flight capped at 1.5 x the largest request, gradients counted twice) and
-    (b) serially with plain FP32 sinograms (1 slot); the arrival rate is
-    `load` times the serial FP32 capacity."""
+    64-hypothesis requests (half cost+gradient).  The same request trace runs
+    in four legs -- serial (1 slot) and served (the continuous-batching server:
+    4 slots, work in flight capped at 1.5 x the largest request, gradients
+    counted twice), each with FP32 and with BF16 sinograms -- so that the gain
+    from batching (served vs serial at one storage type) is apart from the gain
+    from storage (BF16 vs FP32).  First every request at once (saturation; the
+    serial FP32 makespan sets the capacity), then Poisson arrivals at each
+    load x that capacity.  Served results are compared with the serial
+    results of the same storage type, bit for bit."""
     import torch
 
     from paper_1806_02637_amd import inputs
     from paper_1806_02637_amd.serve import Server, latency_summary, poisson_arrivals, replay
 
     wls = inputs.serve_workloads()
-    scans = {"bf16": [], "f32": []}
+    kinds = sorted({kind for _, kind, _ in legs})
+    scans = {k: [] for k in kinds}
     for wl in wls:
         g = wl.geom
         imgs = inputs.project(g, wl.phantom(), device="cuda", as_tensor=True)
-        for dt in ("bf16", "f32"):
+        for dt in kinds:
             sc = eng.load_scan(g.projection_matrices(), g.intrinsics(), imgs)
             sc.build_sinograms(wl.n_alpha, wl.n_t, wl.ds_px, dt)
             scans[dt].append(sc)
         del imgs
         torch.cuda.empty_cache()
+    _log(f"serve: {len(wls)} scans resident in {kinds}")
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(n_requests):
         j = int(rng.integers(len(wls)))
         wl = wls[j]
         reqs.append((j, inputs.random_motion(int(rng.integers(1 << 30)), wl.B, wl.geom.n_views), bool(i % 2)))
-    evals = sum(wls[j].B * wls[j].n_pairs * wls[j].K for j, _, _ in reqs)
+    evals = sum(wls[j].B * wls[j].n_pairs * wls[j].K * (2 if gr else 1) for j, _, gr in reqs)
     work_cap = 1.5 * max(2.0 * wl.B * wl.n_pairs * wl.K for wl in wls)
-    caps = {1: 0.0, 4: work_cap}
 
     def trace(kind, arrivals):
         return [(float(arrivals[i]), scans[kind][j], th, wls[j].K, wls[j].R_mm, g)
                 for i, (j, th, g) in enumerate(reqs)]
 
-    # saturation: every request arrives at once; the serial FP32 makespan
-    # also sets the capacity the Poisson rate is scaled to
-    burst = {}
-    for name, kind, slots in (("serial_f32", "f32", 1), ("served_bf16", "bf16", 4)):
-        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30, work_cap=caps[slots])
-        _, span = replay(srv, trace(kind, np.zeros(n_requests)))
-        srv.close()
-        burst[name] = {"makespan_s": span, "evals_per_s": evals / span, "slots": slots}
-    busy = burst["serial_f32"]["makespan_s"]
-    rate = load * n_requests / busy
-    arrivals = poisson_arrivals(rate, n_requests, seed)
-    out = {"requests": n_requests, "arrival_rate_per_s": rate, "load_vs_serial_f32_capacity": load,
-           "scans_views": [wl.geom.n_views for wl in wls], "hypotheses_per_request": 64, "grad_fraction": 0.5,
-           "served_work_cap": work_cap, "burst": burst}
-    for name, kind, slots in (("served_bf16", "bf16", 4), ("serial_f32", "f32", 1)):
-        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30, work_cap=caps[slots])
-        res, makespan = replay(srv, trace(kind, arrivals))
+    def run(name, kind, slots, arrivals):
+        srv = Server(eng, n_slots=slots, arena_bytes=8 << 30, work_cap=work_cap if slots > 1 else 0.0)
+        res, span = replay(srv, trace(kind, arrivals))
         srv.close()
         lat = latency_summary(res)
-        out[name] = {"p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"], "mean_ms": lat["mean_ms"],
-                     "makespan_s": makespan, "evals_per_s": evals / makespan, "slots": slots}
+        _log(f"serve: {name} done in {span:.2f} s (p50 {lat['p50_ms']:.1f} ms, p99 {lat['p99_ms']:.1f} ms)")
+        return res, span, lat
+
+    out = {"requests": n_requests, "scans_views": [wl.geom.n_views for wl in wls], "hypotheses_per_request": 64,
+           "grad_fraction": 0.5, "served_work_cap": work_cap, "slots": {n: sl for n, _, sl in legs},
+           "evals_per_trace": evals, "note": "evals count a cost+gradient request twice"}
+    # saturation: every request at once
+    burst, costs = {}, {}
+    for name, kind, slots in legs:
+        res, span, lat = run(name, kind, slots, np.zeros(n_requests))
+        burst[name] = {"makespan_s": span, "evals_per_s": evals / span, "p50_ms": lat["p50_ms"],
+                       "p99_ms": lat["p99_ms"]}
+        costs[name] = np.concatenate([r.cost for r in res])
+    out["burst"] = burst
+    out["batching_gain"] = {k: burst[f"served_{k}"]["evals_per_s"] / burst[f"serial_{k}"]["evals_per_s"]
+                            for k in kinds if f"served_{k}" in burst and f"serial_{k}" in burst}
+    out["served_equals_serial_bitwise"] = {k: bool(np.array_equal(costs[f"served_{k}"], costs[f"serial_{k}"]))
+                                           for k in kinds if f"served_{k}" in costs and f"serial_{k}" in costs}
+    capacity = burst[legs[0][0]]["makespan_s"]
+    out["capacity_leg"] = legs[0][0]
+    for load in loads:
+        rate = load * n_requests / capacity
+        arrivals = poisson_arrivals(rate, n_requests, seed + int(load * 1000))
+        point = {"arrival_rate_per_s": rate}
+        for name, kind, slots in legs:
+            _, span, lat = run(name, kind, slots, arrivals)
+            point[name] = {"p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"], "mean_ms": lat["mean_ms"],
+                           "max_ms": lat["max_ms"], "makespan_s": span, "evals_per_s": evals / span}
+        out[f"load_{load}"] = point
     for lst in scans.values():
         for sc in lst:
             sc.free()
     return out
+
+
+def trace_overlap(csv_path):
+    """Overlap of the engine's kernels (namespace ecc::) from different
+    streams in a rocprofv3 kernel trace (CSV): the time with kernels of two or
+    more streams running at once, against the time any of them runs."""
+    import csv
+
+    rows = [r for r in csv.DictReader(open(csv_path)) if "ecc::" in r["Kernel_Name"]]
+    qcol = "Stream_Id" if rows and "Stream_Id" in rows[0] and len({r["Stream_Id"] for r in rows}) > 1 else "Queue_Id"
+    ev = []
+    names = {}
+    for r in rows:
+        t0, t1, q = int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r[qcol]
+        ev.append((t0, 1, q))
+        ev.append((t1, -1, q))
+        names.setdefault(q, {}).setdefault(r["Kernel_Name"].split("(")[0][:60], 0)
+        names[q][r["Kernel_Name"].split("(")[0][:60]] += 1
+    ev.sort(key=lambda e: (e[0], e[1]))
+    active = {}
+    busy = multi = 0
+    peak = 0
+    last = ev[0][0] if ev else 0
+    for t, d, q in ev:
+        n_q = sum(1 for v in active.values() if v > 0)
+        if n_q >= 1:
+            busy += t - last
+        if n_q >= 2:
+            multi += t - last
+        last = t
+        active[q] = active.get(q, 0) + d
+        peak = max(peak, sum(1 for v in active.values() if v > 0))
+    return {"kernels": len(rows), "queues_by": qcol, "queues": len(names),
+            "kernels_per_queue": {q: sum(v.values()) for q, v in names.items()},
+            "busy_ms": busy * 1e-6, "two_or_more_queues_ms": multi * 1e-6,
+            "overlap_fraction_of_busy": multi / busy if busy else 0.0, "max_queues_at_once": peak}
 
 
 def main():
@@ -489,9 +590,18 @@ def main():
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (counter calibration) and exit")
+    ap.add_argument("--no-gather-probe", action="store_true", help="skip the measured gather peaks")
+    ap.add_argument("--serve-only", type=int, default=0, metavar="N",
+                    help="only run the served BF16 leg (4 slots) with N requests, all at once and at load 0.8 "
+                         "(for a kernel trace)")
+    ap.add_argument("--trace-overlap", default=None, metavar="CSV",
+                    help="summarise kernel overlap across queues in a rocprofv3 kernel-trace CSV and exit")
     args = ap.parse_args()
     if args.print_source_hash:
         print(fwd_source_hash())
+        return
+    if args.trace_overlap:
+        print(json.dumps(trace_overlap(args.trace_overlap), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the engine has no multi-GPU path",
@@ -510,6 +620,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 5}))
+        return
+
+    if args.serve_only:
+        eng = engine.Engine(0)
+        legs = (("served_bf16", "bf16", 4),)
+        print(json.dumps(measure_serving(eng, n_requests=args.serve_only, loads=(0.8,), legs=legs)), flush=True)
+        eng.close()
         return
 
     w = inputs.WORKLOADS[args.workload]
@@ -585,6 +702,11 @@ def main():
         "sino_build": {"ms": build_ms, "cells_per_s": cells / (build_ms * 1e-3),
                        "line_samples_per_s_upper": cells * n_s / (build_ms * 1e-3)},
     }
+    if not args.no_gather_probe:
+        _log("gather peaks (L2, Infinity Cache, HBM)")
+        peaks = measure_gather_peaks()
+        rec["gather_peaks"] = peaks
+        rec["roofline"]["gather_rate_vs_l2_random_peak"] = achieved / peaks["l2_random_gbs"]
     # per-pair values for the oracle check; only with the CPU baseline, whose
     # pass supplies the oracle's values (extra launches would also mix into
     # profiler averages of the timed kernel)
