@@ -173,6 +173,9 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
                                                       const PairConst<G> *__restrict__ table, EvalConsts ec,
                                                       float *__restrict__ sens, double *__restrict__ partials,
                                                       int n_tiles) {
+    // the plane angle's row offsets stay in vector registers (a select
+    // cannot take two scalar operands)
+    asm volatile("" : "+v"(ec.rows_half_pi), "+v"(ec.rows_pi));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int Q = pair_split(ec.B), hpb = kWavesPerBlock / Q;
@@ -214,8 +217,8 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         g_sincos(pc.k0 + (G)lane * pc.dk, &sn, &cs);
         for (int i = 0; i < n_sweeps; ++i) {
             const bool last = has_tail & (i == n_sweeps - 1);
-            const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
-            const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
+            const LineCoord<G> ca = line_coord<G, Tap::kAsinTerms>(pc.ha, cs, sn, ec);
+            const LineCoord<G> cb = line_coord<G, Tap::kAsinTerms>(pc.hb, cs, sn, ec);
             const Taps ta = load_taps<Tap, G>(ca, sa, ec);
             const Taps tb = load_taps<Tap, G>(cb, sb, ec);
             const bool hit = (!last | in_tail) & ca.hit & cb.hit;

@@ -141,22 +141,24 @@ hipError_t launch_pair_setup(const float *view_scale, const ViewGeom *vt, EvalCo
 }
 
 // One plane of one pair between issuing its gathers and combining them: the
-// taps in flight plus everything the combine needs (bilinear fractions,
-// Grangeat weights with the storage scale, hit test, relative fold sign).
+// raw taps in flight (converted only in the combine) plus everything the
+// combine needs (bilinear fractions, Grangeat weights with the storage scale,
+// hit test, relative fold sign).
+template <class Tap>
 struct PlaneInFlight {
-    Taps ta, tb;
+    typename Tap::Raw ta, tb;
     float fa_a, ft_a, w_a, fa_b, ft_b, w_b;
     bool hit, flip;
     uint64_t mask;  // wave mask of `hit`
 };
 
 template <class Tap, class G>
-__device__ __forceinline__ void issue_plane(PlaneInFlight &P, const PairConst<G> &pc, G cs, G sn, const Tap *sa,
-                                            const Tap *sb, const EvalConsts &ec) {
-    const LineCoord<G> ca = line_coord<G>(pc.ha, cs, sn, ec);
-    const LineCoord<G> cb = line_coord<G>(pc.hb, cs, sn, ec);
-    P.ta = load_taps<Tap, G>(ca, sa, ec);
-    P.tb = load_taps<Tap, G>(cb, sb, ec);
+__device__ __forceinline__ void issue_plane(PlaneInFlight<Tap> &P, const PairConst<G> &pc, G cs, G sn,
+                                            const Tap *sa, const Tap *sb, const EvalConsts &ec) {
+    const LineCoord<G> ca = line_coord<G, Tap::kAsinTerms>(pc.ha, cs, sn, ec);
+    const LineCoord<G> cb = line_coord<G, Tap::kAsinTerms>(pc.hb, cs, sn, ec);
+    P.ta = fetch_taps<Tap, G>(ca, sa, ec);
+    P.tb = fetch_taps<Tap, G>(cb, sb, ec);
     P.fa_a = ca.fa;
     P.ft_a = ca.ft;
     P.fa_b = cb.fa;
@@ -172,10 +174,11 @@ __device__ __forceinline__ void issue_plane(PlaneInFlight &P, const PairConst<G>
 // (U_a -+ U_b)^2 with U the unsigned samples: only the relative fold sign
 // matters.  `valid` masks the lanes past K in the last sweep, `count_mask`
 // the same lanes in the hit count.
-__device__ __forceinline__ void combine_plane(const PlaneInFlight &P, bool valid, uint64_t count_mask, float &acc,
-                                              int &cnt) {
-    const float Ua = P.w_a * bilerp(P.ta, P.fa_a, P.ft_a);
-    const float Ub = P.w_b * bilerp(P.tb, P.fa_b, P.ft_b);
+template <class Tap>
+__device__ __forceinline__ void combine_plane(const PlaneInFlight<Tap> &P, bool valid, uint64_t count_mask,
+                                              float &acc, int &cnt) {
+    const float Ua = P.w_a * bilerp(Tap::unpack(P.ta), P.fa_a, P.ft_a);
+    const float Ub = P.w_b * bilerp(Tap::unpack(P.tb), P.fa_b, P.ft_b);
     const float d = (P.hit & valid) ? Ua - (P.flip ? -Ub : Ub) : 0.0f;
     acc = fmaf(d, d, acc);
     cnt += __popcll(P.mask & count_mask);
@@ -197,6 +200,9 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     // the column offset joins an FMA with two other scalar operands: keep it
     // in a vector register for the whole kernel rather than copy it per plane
     asm volatile("" : "+v"(ec.t0_tau));
+    // so are the plane angle's two row offsets (a select cannot take two
+    // scalar operands)
+    asm volatile("" : "+v"(ec.rows_half_pi), "+v"(ec.rows_pi));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int Q = pair_split(ec.B), hpb = kWavesPerBlock / Q;
@@ -240,15 +246,16 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
             cs = c2;
         };
         // sweep i is the partial last one when has_tail and i = n_sweeps - 1
-        auto combine = [&](const PlaneInFlight &P, int i) {
+        auto combine = [&](const PlaneInFlight<Tap> &P, int i) {
             const bool last = has_tail & (i == n_sweeps - 1);
             combine_plane(P, !last | in_tail, last ? tail_mask : ~0ull, acc, cnt);
         };
         {
             // two buffers, swapped by unrolling (no register copies); the
             // steady state issues unconditionally so that each combine waits
-            // only for its own gathers
-            PlaneInFlight P0, P1;
+            // only for its own gathers (deeper pipelines, 3 or 4 planes in
+            // flight, measured no faster)
+            PlaneInFlight<Tap> P0, P1;
             issue_plane<Tap, G>(P0, pc, cs, sn, sa, sb, ec);
             rotate();
             int i = 0;

@@ -57,6 +57,14 @@ struct ViewGeomGrad {
     double dC[6][3];
 };
 
+// Terms of the plane-angle polynomial (in sinogram rows, FP32 plane geometry)
+// per storage form: 7 with FP32 storage (1.6e-7 rad, the rounding of an FP32
+// angle near pi), 6 with 16-bit storage (3.9e-7 rad, 1e-4 of a row at 768 rows,
+// far below the rounding of the stored values).  The host fills
+// EvalConsts::asin_rows for the same count.
+constexpr int kAsinTermsF32 = 7;
+constexpr int kAsinTerms16 = 6;
+
 // Scan-wide constants of an evaluation.
 struct EvalConsts {
     int32_t n_views, n_pairs, K, B;
@@ -70,6 +78,11 @@ struct EvalConsts {
     float t0_tau, inv_dt, inv_dalpha;
     int32_t kappa_detector;  // 1: planes sample the arc both detectors see (else the object sphere's)
     double t0_tau_d, inv_dt_d, inv_dalpha_d;
+    // FP32 plane angle in sinogram rows (alpha / dalpha): the asin
+    // coefficients of the storage type's fit times 1 / dalpha, and the
+    // offsets pi/2 and pi in rows
+    float asin_rows[7];
+    float rows_half_pi, rows_pi;
 };
 
 // Pair index <-> (a, b), a < b, row-major triangle.

@@ -17,6 +17,7 @@
 #include "../../include/ecc.h"
 #include "ecc_internal.hpp"
 #include "fdk.hpp"
+#include "poly_coeffs.hpp"
 
 using namespace ecc;
 
@@ -216,6 +217,14 @@ EvalConsts make_consts(const Scan *s, int B, const ecc_eval_params *prm) {
     ec.t0_tau = (float)((t_max + dt) / dt);
     ec.inv_dt = (float)(1.0 / dt);
     ec.inv_dalpha = (float)(1.0 / dalpha);
+    // the plane angle's polynomial for this storage type, in rows
+    const int dtype = s->layout.dtype;
+    static_assert(kAsinTermsF32 == 7 && kAsinTerms16 == 6, "coefficient tables: kAsin (7 terms), kAsin6 (6)");
+    const float *c = dtype == 0 ? kAsin : kAsin6;
+    const int n = dtype == 0 ? kAsinTermsF32 : kAsinTerms16;
+    for (int i = 0; i < 7; ++i) ec.asin_rows[i] = i < n ? (float)((double)c[i] / dalpha) : 0.0f;
+    ec.rows_half_pi = (float)(0.5 * s->layout.n_alpha);
+    ec.rows_pi = (float)s->layout.n_alpha;
     return ec;
 }
 

@@ -65,35 +65,45 @@ struct Taps {
 typedef float f32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
+// Each storage type loads a cell's taps as raw words (fetch) and converts
+// them (unpack) separately, so that a kernel can keep the raw words of a
+// plane in flight and convert them only when it combines the plane.
 struct TapF32 {
     static constexpr bool kScaled = false;
+    static constexpr int kAsinTerms = kAsinTermsF32;
+    using Raw = f32x4_a8;
     float lo, hi;
-    static __device__ __forceinline__ Taps load(const TapF32 *p) {
-        const f32x4_a8 v = *(const f32x4_a8 *)p;
-        return Taps{v.x, v.y, v.z, v.w};
-    }
+    static __device__ __forceinline__ Raw fetch(const TapF32 *p) { return *(const f32x4_a8 *)p; }
+    static __device__ __forceinline__ Taps unpack(const Raw &v) { return Taps{v.x, v.y, v.z, v.w}; }
+    static __device__ __forceinline__ Taps load(const TapF32 *p) { return unpack(fetch(p)); }
 };
 
 struct TapBF16 {
     static constexpr bool kScaled = false;
+    static constexpr int kAsinTerms = kAsinTerms16;
+    using Raw = u32x2_a4;
     uint32_t bits;
-    static __device__ __forceinline__ Taps load(const TapBF16 *p) {
-        const u32x2_a4 v = *(const u32x2_a4 *)p;
+    static __device__ __forceinline__ Raw fetch(const TapBF16 *p) { return *(const u32x2_a4 *)p; }
+    static __device__ __forceinline__ Taps unpack(const Raw &v) {
         return Taps{__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u), __uint_as_float(v.y << 16),
                     __uint_as_float(v.y & 0xFFFF0000u)};
     }
+    static __device__ __forceinline__ Taps load(const TapBF16 *p) { return unpack(fetch(p)); }
 };
 
 struct TapF16 {
     static constexpr bool kScaled = true;  // per-view power-of-two storage scale
+    static constexpr int kAsinTerms = kAsinTerms16;
+    using Raw = u32x2_a4;
     uint32_t bits;
     static __device__ __forceinline__ float h2f(uint32_t h) {
         return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
     }
-    static __device__ __forceinline__ Taps load(const TapF16 *p) {
-        const u32x2_a4 v = *(const u32x2_a4 *)p;
+    static __device__ __forceinline__ Raw fetch(const TapF16 *p) { return *(const u32x2_a4 *)p; }
+    static __device__ __forceinline__ Taps unpack(const Raw &v) {
         return Taps{h2f(v.x & 0xFFFFu), h2f(v.x >> 16), h2f(v.y & 0xFFFFu), h2f(v.y >> 16)};
     }
+    static __device__ __forceinline__ Taps load(const TapF16 *p) { return unpack(fetch(p)); }
 };
 
 // ---- precision-generic helpers ----------------------------------------------
@@ -120,17 +130,19 @@ __device__ __forceinline__ void g_sincos(double x, double *s, double *c) { sinco
 // component, theta = atan(min / max) in [0, pi/4]; then
 //   swap (|y| > |x|): pi/2 - theta;  xneg: pi - (...)
 // combined as off + sgn theta with off in {0, pi/2, pi} and sgn = +-1.
-// FP32 takes theta = asin(min / |(x, y)|) by the fitted polynomial (no
-// reciprocal: the inverse norm is shared with t); FP64 takes atan(min / max).
-__device__ __forceinline__ float g_angle(float ax, float ay, float rinv, bool xneg) {
+// FP32 takes theta = asin(min / |(x, y)|) by a fitted polynomial of NT terms
+// (no reciprocal: the inverse norm is shared with t) whose coefficients and
+// offsets come scaled by 1 / dalpha, so the result is already in sinogram
+// rows; FP64 takes atan(min / max) in radians.
+template <int NT>
+__device__ __forceinline__ float g_angle_rows(float ax, float ay, float rinv, bool xneg, const EvalConsts &ec) {
     const bool swap = ay > ax;
     const float s = (swap ? ax : ay) * rinv;
     const float s2 = s * s;
-    constexpr int n = sizeof(kAsin) / sizeof(kAsin[0]);
-    float p = kAsin[n - 1];
+    float p = ec.asin_rows[NT - 1];
 #pragma unroll
-    for (int i = n - 2; i >= 0; --i) p = fmaf(p, s2, kAsin[i]);
-    const float off = swap ? 1.57079632679489662f : (xneg ? 3.14159265358979324f : 0.0f);
+    for (int i = NT - 2; i >= 0; --i) p = fmaf(p, s2, ec.asin_rows[i]);
+    const float off = swap ? ec.rows_half_pi : (xneg ? ec.rows_pi : 0.0f);
     return fmaf(swap != xneg ? -s : s, p, off);
 }
 __device__ __forceinline__ double g_angle(double ax, double ay, double, bool xneg) {
@@ -205,7 +217,7 @@ struct LineCoord {
     bool hit, fold;      // fold: the line was negated (sign -1 on S)
 };
 
-template <class G>
+template <class G, int NT = 7>
 __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, const EvalConsts &ec) {
     LineCoord<G> c;
     const G l1 = h[0] * cs + h[3] * sn;
@@ -223,7 +235,12 @@ __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, con
     c.rinv = g_rsqrt(r2);
     // the folded l1 is negative iff exactly one of (l1 < 0, fold) holds; at
     // l1 = 0 both quadrant choices give pi/2
-    const G alpha = g_angle(fabs(l1), fabs(l2), c.rinv, (l1 < (G)0) != fold);
+    const bool xneg = (l1 < (G)0) != fold;
+    G rows;  // alpha / dalpha
+    if constexpr (sizeof(G) == 4)
+        rows = g_angle_rows<NT>(fabs(l1), fabs(l2), c.rinv, xneg, ec);
+    else
+        rows = g_angle(fabs(l1), fabs(l2), c.rinv, xneg) * GConst<G>::inv_dalpha(ec);
     const G t = -c.l3 * c.rinv;
     // closed detector rectangle of pixel edges:
     // |t| <= (W/2)|cos a| + (H/2)|sin a|  <=>  |l3| <= (W/2)|l1| + (H/2)|l2|
@@ -232,7 +249,7 @@ __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, con
     // alpha <= pi (rounded up by at most an ulp) puts row m <= n_alpha: the
     // stored cell rows run to n_alpha, whose upper row continues the
     // sinogram past pi
-    c.fa = cell_split(alpha * GConst<G>::inv_dalpha(ec), (G)ec.n_alpha, c.m);
+    c.fa = cell_split(rows, (G)ec.n_alpha, c.m);
     // stored column coordinate: column j holds t_{j-1}, so j = tau with
     // tau = (t + t_max + dt) / dt = t / dt + t0_tau
     const G tau = fma(t, GConst<G>::inv_dt(ec), GConst<G>::t0_tau(ec));
@@ -256,9 +273,18 @@ __device__ __forceinline__ uint64_t hit_mask(const LineCoord<G> &c) {
 // the byte offset is a 32-bit value added to the view's base address, and
 // m, j < 2^24 allow the 24-bit multiply-add.
 template <class Tap, class G>
-__device__ __forceinline__ Taps load_taps(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec) {
+__device__ __forceinline__ const Tap *tap_address(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec) {
     const uint32_t e = __umul24((uint32_t)c.m, (uint32_t)ec.row_elems) + (uint32_t)c.j;
-    return Tap::load((const Tap *)((const char *)sview + e * (uint32_t)sizeof(Tap)));
+    return (const Tap *)((const char *)sview + e * (uint32_t)sizeof(Tap));
+}
+template <class Tap, class G>
+__device__ __forceinline__ Taps load_taps(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec) {
+    return Tap::load(tap_address<Tap, G>(c, sview, ec));
+}
+template <class Tap, class G>
+__device__ __forceinline__ typename Tap::Raw fetch_taps(const LineCoord<G> &c, const Tap *sview,
+                                                        const EvalConsts &ec) {
+    return Tap::fetch(tap_address<Tap, G>(c, sview, ec));
 }
 
 // Bilinear interpolation of a cell's taps at fractions (fa along alpha, ft
