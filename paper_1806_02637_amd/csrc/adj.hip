@@ -1,8 +1,8 @@
 // Adjoint of the consistency cost: d cost / d theta for every view's six
 // motion parameters, with the line geometry recomputed rather than stored.
 //
-// ecc_adj       same work split as the forward kernel (4 hypotheses x one
-//               pair tile per workgroup).  Per pair:
+// ecc_adj       same work split as the forward kernel (one hypothesis x one
+//               pair tile per workgroup, 16 pairs per wave).  Per pair:
 //                 1. forward sweep over the K planes -> d, N (Eq. 15), e (Eq. 16);
 //                 2. reverse sweep over the planes: dE/dS_a = +g, dE/dS_b = -g with
 //                    g = de/dd * 2 (S_a - S_b) / N on planes hitting both
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
     const int hyp = (int)(w % hyp_groups) * hpb + wave % hpb;
     const int part = wave / hpb, q_per = kPairsPerWave / Q;
     // a wave without a hypothesis exists only when Q = 1, where no barrier
-    // follows; with Q > 1 every wave has one (hpb = B)
+    // follows; with Q > 1 every wave has one (hpb <= B)
     if (hyp >= ec.B) return;
     __shared__ double part_acc[kWavesPerBlock];
     __shared__ PairConst<G> slots[kWavesPerBlock][kPairsPerWave];

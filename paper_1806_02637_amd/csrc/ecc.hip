@@ -5,9 +5,9 @@
 // pair_setup   one thread per (hypothesis, pair): the pair's geometry in FP64
 //              (baseline, pencil of planes, the two line maps of Eq. 14) ->
 //              a table of per-plane constants.
-// ecc_fwd      a workgroup = 4 waves = 4 hypotheses of one tile of up to 64
-//              view pairs (8 x 8 view blocks); a wave walks its pairs
-//              (constants staged in LDS) with lanes along the plane angle kappa: line ->
+// ecc_fwd      a workgroup = one hypothesis x one tile of up to 64 view
+//              pairs (8 x 8 view blocks), 16 pairs per wave; a wave walks its
+//              pairs (constants staged in LDS) with lanes along the plane angle kappa: line ->
 //              (alpha, t) -> four bilinear taps per view in one load ->
 //              (S_a - S_b)^2 -> wave-shuffle sum (Eq. 15) -> Cauchy norm
 //              (Eq. 16).  No atomics; per-tile FP64 partials.
@@ -184,9 +184,9 @@ __device__ __forceinline__ void combine_plane(const PlaneInFlight<Tap> &P, bool 
     cnt += __popcll(P.mask & count_mask);
 }
 
-// A wave = one hypothesis x one pair tile; a workgroup = 4 hypotheses of the
-// same tile (they read nearly the same sinogram cells), or with B <= 2 the
-// hypotheses' tile split into parts over the 4 waves (pair_split).  Lanes
+// A workgroup = one hypothesis x one pair tile, the tile's 64 pairs split
+// into 4 parts over its waves (pair_split); consecutive workgroups are the
+// same tile's other hypotheses, which read nearly the same sinogram cells.  Lanes
 // walk the planes k = lane + 64 i; the trip count is wave-uniform (K / 64
 // full sweeps plus a masked tail) and the hit count is a population count of
 // the hit mask.  The gathers of sweep i + 1 are issued before sweep i is
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
     const int hyp = (int)(w % hyp_groups) * hpb + wave % hpb;
     const int part = wave / hpb, q_per = kPairsPerWave / Q;
     // a wave without a hypothesis exists only when Q = 1, where no barrier
-    // follows; with Q > 1 every wave has one (hpb = B)
+    // follows; with Q > 1 every wave has one (hpb <= B)
     if (hyp >= ec.B) return;
     __shared__ double part_acc[kWavesPerBlock];
     __shared__ PairConst<G> slots[kWavesPerBlock][kPairsPerWave];
@@ -253,8 +253,8 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
         {
             // two buffers, swapped by unrolling (no register copies); the
             // steady state issues unconditionally so that each combine waits
-            // only for its own gathers (deeper pipelines, 3 or 4 planes in
-            // flight, measured no faster)
+            // only for its own gathers (three planes in flight measured no
+            // faster at B = 32 on the 496-view scan, with any storage form)
             PlaneInFlight<Tap> P0, P1;
             issue_plane<Tap, G>(P0, pc, cs, sn, sa, sb, ec);
             rotate();
@@ -302,8 +302,8 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
 
 // Occupancy cap of the plane kernels: workgroups per CU, enforced through an
 // unused dynamic LDS allocation (160 KB per CU).  More resident waves than
-// this widen the set of pair tiles in flight per XCD beyond what its L2 can
-// hold, and L2 misses grow faster than latency hiding gains.
+// this widen the set of pair tiles in flight per XCD, and L2 misses grow
+// faster than latency hiding gains.
 size_t occupancy_lds_bytes(size_t static_bytes, int cap) {
     if (cap <= 0) return 0;
     size_t b = (160u * 1024u) / (size_t)cap;
@@ -318,8 +318,7 @@ static hipError_t launch_fwd_t(const void *sino, const void *table, EvalConsts e
     const int64_t total = plane_work_items(ec.B, n_tiles);
     const int64_t blocks = 8 * ((total + 7) / 8);
     hipLaunchKernelGGL((ecc_fwd_kernel<Tap, G>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock),
-                       occupancy_lds_bytes(plane_kernel_lds<G>(),
-                                           sizeof(Tap) == 8 ? kFwdBlocksPerCU32 : kFwdBlocksPerCU16),
+                       occupancy_lds_bytes(plane_kernel_lds<G>(), kFwdBlocksPerCU),
                        s, sino, (const PairConst<G> *)table, ec, out_pair, out_count, partials, n_tiles);
     return hipGetLastError();
 }

@@ -141,11 +141,11 @@ constexpr int kPairsPerWave = 64;
 // zero border (pixels) around the weighted projections read by the line sums
 constexpr int kImgPad = 3;
 constexpr int kWavesPerBlock = 4;
-// default caps on resident plane-kernel workgroups per CU (0 = no cap): the
-// forward kernel with 16-byte gathers (FP32 storage) 3, with 8-byte gathers
-// (BF16, FP16) 4, the adjoint 4
-constexpr int kFwdBlocksPerCU32 = 3;
-constexpr int kFwdBlocksPerCU16 = 4;
+// caps on resident plane-kernel workgroups per CU (0 = no cap), 4 for the
+// forward kernel with every storage form and for the adjoint (at B = 32 on
+// the 496-view scan: the FP32 forward kernel at 3 is 2 % slower, 5 or 6 are
+// no faster for any form; the adjoint at 3 is 17 % slower)
+constexpr int kFwdBlocksPerCU = 4;
 constexpr int kAdjBlocksPerCU = 4;
 // dynamic LDS that, added to a kernel's static LDS, caps resident
 // workgroups per CU at `cap` (0 = no cap)

@@ -104,7 +104,15 @@ __device__ __forceinline__ float wave_sum(float x) {
 // or the 28 pairs inside one block (I == J).  The 8 neighbouring sources of a
 // block give similar pencils in each view of the other block, so a tile
 // touches 16 views' sinograms with high reuse.  Tiles run row by row
-// (I fixed, J increasing).
+// (I fixed, J increasing), so the tiles in flight on one XCD share block I.
+// Inside a tile a wave walks the pairs with the block-J view b fixed for 8
+// consecutive pairs while the block-I view a changes: the block-I views'
+// lines are largely common to all tiles in flight and stay in L2 until a view
+// comes back 8 pairs later, while each tile's own view b is reused at once.
+// (With a fixed and b walking, every tile's b comes back only after 8 pairs,
+// by when the other tiles' bands have evicted it: an LRU model of one XCD's
+// 4 MB L2 over 12 tiles x 32 hypotheses of the 496-view scan gives 4.9x
+// fewer misses this way, within 3 % of the compulsory ones.)
 constexpr int kViewBlock = 8;
 
 __host__ __device__ inline int n_view_blocks(int n_views) { return (n_views + kViewBlock - 1) / kViewBlock; }
@@ -125,8 +133,8 @@ __device__ __forceinline__ bool tile_pair(int tile, int q, int n_views, int &a, 
     while (I < nb - 1 && (I + 1) * nb - (I + 1) * I / 2 <= tile) ++I;
     const int J = tile - (I * nb - I * (I - 1) / 2) + I;
     if (I < J) {
-        a = I * kViewBlock + q / kViewBlock;
-        b = J * kViewBlock + q % kViewBlock;
+        a = I * kViewBlock + q % kViewBlock;
+        b = J * kViewBlock + q / kViewBlock;
     } else {
         if (q >= kViewBlock * (kViewBlock - 1) / 2) return false;
         int i, j;
@@ -155,12 +163,17 @@ __device__ __forceinline__ void stage_tile(PairConst<G> *slots, const PairConst<
 }
 
 // Waves of a workgroup: kWavesPerBlock / Q hypotheses of one pair tile, each
-// tile's pairs split into Q parts, Q = pair_split(B).  With fewer
-// hypotheses than waves the spare waves take parts of the same tiles, so that
-// a B = 1 evaluation (one L-BFGS step) has four times the waves in flight it
-// would have with one wave per tile; the parts' sums are added in a fixed
-// order.
-__host__ __device__ inline int pair_split(int B) { return B == 1 ? 4 : (B == 2 ? 2 : 1); }
+// tile's pairs split into Q parts, Q = pair_split(B); the parts' sums are
+// added in a fixed order.  Q = kWavesPerBlock for every B: a workgroup is one
+// hypothesis of one tile, its waves taking 16 pairs each, and consecutive
+// workgroups on an XCD are the same tile's next hypotheses.  The XCD then
+// holds all hypotheses of a few tiles rather than four hypotheses of many, a
+// smaller set of sinogram lines in flight (at B = 32 on the 496-view scan the
+// forward kernel ran 2-4 % and the adjoint 7 % faster than with four
+// hypotheses of a tile per workgroup), and a B = 1 evaluation (one L-BFGS
+// step) has four times the waves in flight it would have with one wave per
+// tile.
+__host__ __device__ inline int pair_split(int) { return kWavesPerBlock; }
 __host__ __device__ inline int64_t plane_work_items(int B, int n_tiles) {
     const int hpb = kWavesPerBlock / pair_split(B);
     return (int64_t)n_tiles * ((B + hpb - 1) / hpb);
