@@ -110,9 +110,9 @@ __device__ __forceinline__ float wave_sum(float x) {
 // lines are largely common to all tiles in flight and stay in L2 until a view
 // comes back 8 pairs later, while each tile's own view b is reused at once.
 // (With a fixed and b walking, every tile's b comes back only after 8 pairs,
-// by when the other tiles' bands have evicted it: an LRU model of one XCD's
-// 4 MB L2 over 12 tiles x 32 hypotheses of the 496-view scan gives 4.9x
-// fewer misses this way, within 3 % of the compulsory ones.)
+// by when the other tiles' lines have evicted it: at B = 32 on the 496-view
+// scan, with four hypotheses of a tile per workgroup, that order measured an
+// L2 hit rate of 0.754 against 0.860 and 9.7 against 9.3 ms per evaluation.)
 constexpr int kViewBlock = 8;
 
 __host__ __device__ inline int n_view_blocks(int n_views) { return (n_views + kViewBlock - 1) / kViewBlock; }
