@@ -29,19 +29,72 @@ HBM_PEAK_GBS = 8000.0
 TAP_BYTES = {"f32": 4, "bf16": 2, "f16": 2}
 
 
-FWD_SOURCES = ("ecc.hip", "lookup.hpp", "pair.hpp", "projective.hpp", "ecc_internal.hpp", "poly_coeffs.hpp")
+FWD_SOURCES = ("ecc.hip", "lookup.hpp", "pair.hpp", "arc.hpp", "projective.hpp", "ecc_internal.hpp", "poly_coeffs.hpp")
 
 
-def fwd_source_hash() -> str:
-    """SHA-256 over the sources the forward kernel is compiled from; HBM counters
-    recorded for another hash describe another kernel."""
+def fwd_source_hash(csrc: str | None = None) -> str:
+    """SHA-256 over the code of the sources the forward kernel is compiled from
+    (comments and whitespace removed, so that only a change of code changes
+    it); HBM counters recorded for another hash describe another kernel."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for name in FWD_SOURCES:
-        with open(os.path.join(ROOT, "paper_1806_02637_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc or os.path.join(ROOT, "paper_1806_02637_amd", "csrc"), name)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
+
+
+def kept_counters(path, workload, dtype, geom):
+    """The kept rocprofv3 counters of the forward kernel (per dispatch) for
+    this storage / geometry form, with the gather probe's and the copy
+    calibration's, or None when they were taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        kc = json.load(fh)
+    if kc.get("workload") != workload or kc.get("source_sha256") != fwd_source_hash():
+        return None
+    form = kc.get("forms", {}).get(f"{dtype}_{geom}")
+    if not form:
+        return None
+    return dict(form, probe=kc["probe"])
+
+
+def binding_fractions(kc, launch_ms, peaks=None):
+    """What limits the forward kernel, from its kept counters and this run's
+    launch time: HBM bytes actually moved (FETCH_SIZE x 2 + WRITE_SIZE, the
+    copy calibration's scales) against the HBM peak; L1 -> L2 read requests
+    (TCP_TCC_READ_REQ x the line size) against the same rate of the gather
+    probe's random 16-byte loads from an L2-resident buffer (its live gather
+    rate when given, turned into requests by its counted requests per
+    gather); VALU issue
+    (SQ_INSTS_VALU x 4 cycles per wave64 instruction over 1024 SIMDs at the
+    clock the kernel ran at, from GRBM_GUI_ACTIVE); the L1's cycles waiting
+    on L2 data."""
+    s = launch_ms * 1e-3
+    pr = kc["probe"]
+    cycles = kc["grbm_gui_active"] / 8.0  # per XCD
+    clock_hz = cycles / (kc["profiled_ms"] * 1e-3)
+    l2_gbs = kc["tcp_tcc_read_req"] * pr["line_bytes"] / s / 1e9
+    if peaks:  # this run's probe rate, in requests through the probe's counted requests per gather
+        l2_peak = peaks["l2_random_gbs"] / 16.0 * pr["l2_random_req_per_gather"] * pr["line_bytes"]
+    else:
+        l2_peak = pr["l2_random_req_per_s"] * pr["line_bytes"] / 1e9
+    hbm = kc["hbm_bytes_per_launch"] / s / 1e9
+    return {
+        "hbm_measured_gbs": hbm, "hbm_measured_frac": hbm / HBM_PEAK_GBS,
+        "l2_gbs": l2_gbs, "l2_peak_measured": l2_peak, "l2_frac": l2_gbs / l2_peak,
+        "valu_busy": kc["sq_insts_valu"] * 4.0 / (1024.0 * clock_hz * kc["profiled_ms"] * 1e-3),
+        "valu_insts_per_eval": kc["valu_lane_insts_per_eval"],
+        "l1_waiting_on_l2": kc["tcp_pending_stall_cycles"] / (256.0 * kc.get("tcp_grbm_gui_active", 8 * cycles) / 8.0),
+        "clock_ghz": clock_hz / 1e9, "l2_line_bytes": pr["line_bytes"],
+        "source": "profiles/ecc_fwd_full496_counters.json (rocprofv3 --pmc, per dispatch)",
+    }
 
 
 def _log(msg):
@@ -77,6 +130,19 @@ def _oracle_share(images, intr, P, thetas, grid_args, K, R_mm, pairs, target_s, 
         run()
         n += 1
     results.put((n * len(thetas) * len(pairs) * K, time.perf_counter() - t0))
+
+
+def host_cpu_model():
+    """The host CPU's model string (Linux /proc/cpuinfo), or the platform's processor name."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
 def cpu_baseline_all_cores(w, host, P, intr, thetas, pairs, n_proc, target_s=12.0):
@@ -180,6 +246,7 @@ def cpu_baseline(w, imgs_dev, P, intr, thetas, target_s=12.0, n_views=12, n_hyp=
         _log(f"oracle: timed pass {passes}, {dt:.1f} s so far")
     evals = passes * n_h * len(pairs) * w.K
     out = {"value": evals / dt, "unit": "plane-pair evals/s", "cores": 1, "kind": "oracle",
+           "host_cpu": host_cpu_model(), "host_threads": os.cpu_count(),
            "sample": f"{len(pairs)} pairs among {n_views} seeded views x {n_h} hypotheses x K={w.K}, "
                      f"evaluated {passes} times ({evals} evals in {dt:.1f} s; an untimed first pass "
                      f"filled the touched sinogram cells in {fill:.1f} s)"}
@@ -240,6 +307,15 @@ def measure_variants(eng, w, P, intr, imgs, scan32, th_dev, steps, pairs_out, n_
     if pairs_out is not None:
         pairs_out["f32_geom64"] = scan32.cost(th_dev[:n_check], w.K, w.R_mm, geom="f64",
                                               with_pairs=True)[1].cpu().numpy()
+    # hit decisions (Eq. 15's N_kappa) of FP32 against FP64 plane geometry,
+    # every plane of every pair of every hypothesis of the step
+    _, n32 = scan32.cost(th_dev, w.K, w.R_mm, workspace=ws, with_counts=True)
+    _, n64 = scan32.cost(th_dev, w.K, w.R_mm, geom="f64", workspace=ws, with_counts=True)
+    dn = (n32.long() - n64.long()).abs()
+    out["hit_flips_f32_vs_f64_geometry"] = {
+        "pairs_with_a_flip": int((dn > 0).sum()), "planes_flipped_at_least": int(dn.sum()),
+        "pairs": int(dn.numel()), "planes": int(dn.numel()) * w.K,
+        "note": "per pair |N_f32 - N_f64| (a pair's count changes by at least its flipped planes' net)"}
     if detector_range:
         ms = timed(lambda: scan32.cost(th_dev, w.K, w.R_mm, workspace=ws, kappa="detector"), steps, 2)
         out["f32_detector_range"] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3),
@@ -535,12 +611,15 @@ def measure_serving(eng, n_requests=200, seed=7, loads=(0.5, 0.8, 0.95), legs=SE
 
 
 def trace_overlap(csv_path):
-    """Overlap of the engine's kernels (namespace ecc::) from different
-    streams in a rocprofv3 kernel trace (CSV): the time with kernels of two or
-    more streams running at once, against the time any of them runs."""
+    """Overlap of the engine's evaluation kernels (namespace ecc::, without
+    the sinogram build and reconstruction kernels that prepare the scans) from
+    different streams in a rocprofv3 kernel trace (CSV): the time with
+    kernels of two or more streams running at once, against the time any of
+    them runs."""
     import csv
 
-    rows = [r for r in csv.DictReader(open(csv_path)) if "ecc::" in r["Kernel_Name"]]
+    rows = [r for r in csv.DictReader(open(csv_path))
+            if "ecc::" in r["Kernel_Name"] and not any(k in r["Kernel_Name"] for k in ("sino_", "fdk_"))]
     qcol = "Stream_Id" if rows and "Stream_Id" in rows[0] and len({r["Stream_Id"] for r in rows}) > 1 else "Queue_Id"
     ev = []
     names = {}
@@ -586,7 +665,7 @@ def main():
     ap.add_argument("--no-fdk", action="store_true", help="skip the FDK reconstruction timing")
     ap.add_argument("--no-detector-range", action="store_true",
                     help="skip the detector-bounded plane range variant (it launches the same forward kernel)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ecc_fwd_full496_traffic.json"))
+    ap.add_argument("--counters-json", default=os.path.join(ROOT, "profiles", "ecc_fwd_full496_counters.json"))
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (counter calibration) and exit")
@@ -672,13 +751,8 @@ def main():
 
     tap_bytes = 8 * TAP_BYTES[args.dtype]  # 2 views x 4 bilinear taps
     achieved = tap_bytes * evals / (per_call_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as fh:
-            tj = json.load(fh)
-        if (tj.get("workload") == w.name and tj.get("dtype") == args.dtype and tj.get("geom") == args.geom
-                and tj.get("source_sha256") == fwd_source_hash()):
-            traffic = tj.get("hbm_bytes_per_launch")
+    kc = kept_counters(args.counters_json, w.name, args.dtype, args.geom)
+    traffic = kc["hbm_bytes_per_launch"] if kc else None
     rec = {
         "metric": METRIC,
         "value": value,
@@ -698,7 +772,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "ecc_fwd_kernel", "algorithmic_bytes_per_eval": tap_bytes,
-                     "launch_ms": per_call_ms},
+                     "launch_ms": per_call_ms,
+                     "target": "achieved / peak: algorithmic gather bytes against the HBM peak (the bandwidth "
+                               "roofline the target is stated on); what actually binds is in 'binding'",
+                     "binding": None},
         "sino_build": {"ms": build_ms, "cells_per_s": cells / (build_ms * 1e-3),
                        "line_samples_per_s_upper": cells * n_s / (build_ms * 1e-3)},
     }
@@ -706,7 +783,10 @@ def main():
         _log("gather peaks (L2, Infinity Cache, HBM)")
         peaks = measure_gather_peaks()
         rec["gather_peaks"] = peaks
-        rec["roofline"]["gather_rate_vs_l2_random_peak"] = achieved / peaks["l2_random_gbs"]
+    else:
+        peaks = None
+    if kc:
+        rec["roofline"]["binding"] = binding_fractions(kc, per_call_ms, peaks)
     # per-pair values for the oracle check; only with the CPU baseline, whose
     # pass supplies the oracle's values (extra launches would also mix into
     # profiler averages of the timed kernel)

@@ -143,8 +143,8 @@ constexpr int kImgPad = 3;
 constexpr int kWavesPerBlock = 4;
 // caps on resident plane-kernel workgroups per CU (0 = no cap), 4 for the
 // forward kernel with every storage form and for the adjoint (at B = 32 on
-// the 496-view scan: the FP32 forward kernel at 3 is 2 % slower, 5 or 6 are
-// no faster for any form; the adjoint at 3 is 17 % slower)
+// the 496-view scan: the FP32 forward kernel at 3 is 2 % slower, the 16-bit
+// forms at 5 or 6 no faster; the adjoint at 3 is 17 % slower)
 constexpr int kFwdBlocksPerCU = 4;
 constexpr int kAdjBlocksPerCU = 4;
 // dynamic LDS that, added to a kernel's static LDS, caps resident
