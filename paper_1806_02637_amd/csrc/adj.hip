@@ -14,9 +14,11 @@
 //                    the detector-bounded range (k = lo + (k+1/2)(hi - lo)/K);
 //                    fixed-order wave sums of those 14 sensitivities, written
 //                    per pair.
-// pair_tangent  one thread per (hypothesis, pair, motion parameter): an FP64
-//               forward-mode (dual number) sweep of the pair's geometry seeded
-//               with dP'/dtheta, contracted with the 14 sensitivities.  A
+// pair_grad     one thread per (hypothesis, pair): the 14 sensitivities taken
+//               back through the pair's geometry in FP64 (one reverse sweep:
+//               line maps -> rows of M = P'[:, 0:3] and the pencil's u1, u2,
+//               kappa_max -> the two sources), then contracted with each of
+//               the 12 motion parameters' dP'/dtheta and dC/dtheta.  A
 //               detector arc's end moves as the zero angle of the corner that
 //               fixes it, atan2(-A_c, B_c) with (A_c, B_c) the two basis
 //               lines' values at the corner.
@@ -28,6 +30,7 @@
 #include "ecc_internal.hpp"
 #include "lookup.hpp"
 #include "pair.hpp"
+#include "pair_adjoint.hpp"
 #include "projective.hpp"
 
 namespace ecc {
@@ -88,79 +91,6 @@ __device__ __forceinline__ float kappa_sum(const G h[6], const float gH[6]) {
     return r;
 }
 
-constexpr int kSens = 14;  // per-pair sensitivities: dE/dHa [6], dE/dHb [6], two for the arc
-
-// Derivative of a detector arc's end, the zero angle atan2(-A, B) of corner
-// c with A, B the values of the (unscaled) basis lines H there.
-__device__ double arc_end_tangent(const Dual H[6], int corner, double hw, double hh) {
-    const double x = (corner & 2) ? hw : -hw, y = (corner & 1) ? hh : -hh;
-    const double A = H[0].v * x + H[1].v * y + H[2].v, B = H[3].v * x + H[4].v * y + H[5].v;
-    const double dA = H[0].d * x + H[1].d * y + H[2].d, dB = H[3].d * x + H[4].d * y + H[5].d;
-    const double r2 = A * A + B * B;
-    return r2 > 0.0 ? (A * dB - B * dA) / r2 : 0.0;
-}
-
-// Directional derivative of (Ha, Hb, sampled arc) along one motion parameter,
-// contracted with the sensitivities g = (dE/dHa [6], dE/dHb [6], arc [2]):
-// arc = (dE/dkappa_max, 0) for the object-sphere range, (dE/dlo, dE/dhi)
-// for the detector-bounded range.
-__device__ double pair_tangent(const ViewGeom &A, const ViewGeom &Bv, const ViewGeomGrad &gA,
-                               const ViewGeomGrad &gB, int dir, const EvalConsts &ec, const float g[kSens]) {
-    Dual Pa[12], Pb[12], Ca[3], Cb[3];
-    const bool on_a = dir < 6;
-    const int q = on_a ? dir : dir - 6;
-    for (int e = 0; e < 12; ++e) {
-        Pa[e] = Dual(A.P[e], on_a ? gA.dP[q][e] : 0.0);
-        Pb[e] = Dual(Bv.P[e], on_a ? 0.0 : gB.dP[q][e]);
-    }
-    for (int e = 0; e < 3; ++e) {
-        Ca[e] = Dual(A.C[e], on_a ? gA.dC[q][e] : 0.0);
-        Cb[e] = Dual(Bv.C[e], on_a ? 0.0 : gB.dC[q][e]);
-    }
-    Dual u1[3], u2[3], km;
-    pencil(Ca, Cb, ec.R_mm, u1, u2, km);
-    Dual Ha[6], Hb[6];
-    line_map(Pa, Ca, u1, u2, A.u0, A.v0, Ha);
-    line_map(Pb, Ca, u1, u2, Bv.u0, Bv.v0, Hb);
-    // the forward pass scaled each map by an exact power of two (the same
-    // exponent follows from the values here); sensitivities were taken with
-    // respect to the scaled maps
-    double ma = 0.0, mb = 0.0;
-    for (int i = 0; i < 6; ++i) {
-        ma = fmax(ma, fabs(Ha[i].v));
-        mb = fmax(mb, fabs(Hb[i].v));
-    }
-    const int ea = ma > 0.0 ? ilogb(ma) : 0, eb = mb > 0.0 ? ilogb(mb) : 0;
-    double ga = 0.0, gb = 0.0;
-    for (int i = 0; i < 6; ++i) {
-        ga += (double)g[i] * Ha[i].d;
-        gb += (double)g[6 + i] * Hb[i].d;
-    }
-    double g_arc;
-    if (ec.kappa_detector) {
-        double va[6], vb[6], lo, hi;
-        for (int i = 0; i < 6; ++i) {
-            va[i] = Ha[i].v;
-            vb[i] = Hb[i].v;
-        }
-        ArcEnd e_lo, e_hi;
-        const double hw = (double)ec.half_w, hh = (double)ec.half_h;
-        // d(end): the zero angle of the corner behind it, the mean of both
-        // views' corners at a tie, 0 for a fixed end
-        auto end_tangent = [&](const ArcEnd &e) {
-            const double ta = e.corner_a >= 0 ? arc_end_tangent(Ha, e.corner_a, hw, hh) : 0.0;
-            const double tb = e.corner_b >= 0 ? arc_end_tangent(Hb, e.corner_b, hw, hh) : 0.0;
-            return e.view == 0 ? ta : e.view == 1 ? tb : e.view == 2 ? 0.5 * (ta + tb) : 0.0;
-        };
-        // an empty arc has zero sensitivities (no plane counts)
-        g_arc = pair_arc(va, vb, hw, hh, lo, hi, &e_lo, &e_hi)
-                    ? (double)g[12] * end_tangent(e_lo) + (double)g[13] * end_tangent(e_hi)
-                    : 0.0;
-    } else {
-        g_arc = (double)g[12] * km.d;
-    }
-    return ldexp(ga, -ea) + ldexp(gb, -eb) + g_arc;
-}
 
 // Cost and the pair sensitivities in one sweep over the planes.  With
 // d = sum (S_a - S_b)^2 / N, e = d / (1 + d / c), every plane's gradient
@@ -270,21 +200,24 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
     }
 }
 
-__global__ __launch_bounds__(256) void pair_tangent_kernel(const ViewGeom *__restrict__ vt,
-                                                           const ViewGeomGrad *__restrict__ vg,
-                                                           const float *__restrict__ sens, EvalConsts ec,
-                                                           float *__restrict__ pair_grad) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)ec.B * ec.n_pairs * 12) return;
-    const int dir = (int)(idx % 12);
-    const int64_t hp = idx / 12;  // hyp * n_pairs + pair
+// One thread per (hypothesis, pair): pair_gradient (pair_adjoint.hpp).
+__global__ __launch_bounds__(256) void pair_grad_kernel(const ViewGeom *__restrict__ vt,
+                                                        const ViewGeomGrad *__restrict__ vg,
+                                                        const float *__restrict__ sens, EvalConsts ec,
+                                                        float *__restrict__ pair_grad) {
+    const int64_t hp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // hyp * n_pairs + pair
+    if (hp >= (int64_t)ec.B * ec.n_pairs) return;
     const int hyp = (int)(hp / ec.n_pairs);
     int a, b;
     pair_from_index(hp % ec.n_pairs, ec.n_views, a, b);
     const int64_t ga = (int64_t)hyp * ec.n_views + a, gb = (int64_t)hyp * ec.n_views + b;
-    float g14[kSens];
-    for (int i = 0; i < kSens; ++i) g14[i] = sens[hp * kSens + i];
-    pair_grad[hp * 12 + dir] = (float)pair_tangent(vt[ga], vt[gb], vg[ga], vg[gb], dir, ec, g14);
+    const ViewGeom &A = vt[ga], &Bv = vt[gb];
+    double g[kSens], out[12];
+    for (int i = 0; i < kSens; ++i) g[i] = (double)sens[hp * kSens + i];
+    const ViewGeomGrad &dA = vg[ga], &dB = vg[gb];
+    pair_gradient(A.P, A.C, A.u0, A.v0, Bv.P, Bv.C, Bv.u0, Bv.v0, dA.dP, dA.dC, dB.dP, dB.dC, ec.R_mm,
+                  ec.kappa_detector != 0, (double)ec.half_w, (double)ec.half_h, g, out);
+    for (int q = 0; q < 12; ++q) pair_grad[hp * 12 + q] = (float)out[q];
 }
 
 template <class Tap, class G>
@@ -312,8 +245,8 @@ hipError_t launch_ecc_adj(const void *sino, const void *table, const ViewGeom *v
         else e = launch_adj_t<TapF16, float>(sino, table, ec, sens, partials, n_tiles, s);
     }
     if (e != hipSuccess) return e;
-    const int64_t n = (int64_t)ec.B * ec.n_pairs * 12;
-    hipLaunchKernelGGL(pair_tangent_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vt, vg, sens, ec,
+    const int64_t n = (int64_t)ec.B * ec.n_pairs;
+    hipLaunchKernelGGL(pair_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vt, vg, sens, ec,
                        pair_grad);
     return hipGetLastError();
 }

@@ -1,7 +1,8 @@
 // Projective-geometry steps on the device, written once for any scalar type
 // T with + - * / and the functions g_sqrt / g_asin / g_val below: T = double
 // for the forward evaluation, T = Dual (value + one directional derivative)
-// for the adjoint's per-pair tangent sweeps.
+// for the sources' derivatives with respect to the motion (view setup) and
+// for the host check of the adjoint's reverse sweep.
 //
 // Method steps (arxiv 1806.02637):
 //  * meet of two planes -> Pluecker line (Eq. 4);
