@@ -176,11 +176,12 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
             g[13] = detector ? s1 : 0.0f;
         }
         acc = wave_sum(acc);
-        const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
+        // d and e through the hardware reciprocal, as in the forward kernel
+        const float d = cnt > 0 ? acc * __builtin_amdgcn_rcpf((float)cnt) : 0.0f;
         const float den = 1.0f + d * ec.inv_c;
-        const float e = ec.inv_c > 0.0f ? d / den : d;
+        const float e = ec.inv_c > 0.0f ? d * __builtin_amdgcn_rcpf(den) : d;
         wave_acc += (double)e;
-        const float coef = cnt > 0 ? 2.0f / ((float)cnt * den * den) : 0.0f;
+        const float coef = cnt > 0 ? 2.0f * __builtin_amdgcn_rcpf((float)cnt * den * den) : 0.0f;
         for (int i = 0; i < kSens; ++i) g[i] = coef * wave_sum(g[i]);
         if (lane == 0) {
             float *out = sens + ((int64_t)hyp * ec.n_pairs + p) * kSens;

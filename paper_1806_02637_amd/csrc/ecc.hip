@@ -281,8 +281,10 @@ __global__ __launch_bounds__(256) void ecc_fwd_kernel(const void *__restrict__ s
             }
         }
         acc = wave_sum(acc);
-        const float d = cnt > 0 ? acc / (float)cnt : 0.0f;
-        const float e = ec.inv_c > 0.0f ? d / (1.0f + d * ec.inv_c) : d;
+        // d and e through the hardware reciprocal (1 ulp; cnt >= 1 and the
+        // Cauchy denominator >= 1), as in the adjoint
+        const float d = cnt > 0 ? acc * __builtin_amdgcn_rcpf((float)cnt) : 0.0f;
+        const float e = ec.inv_c > 0.0f ? d * __builtin_amdgcn_rcpf(1.0f + d * ec.inv_c) : d;
         if (out_pair && lane == 0) out_pair[(int64_t)hyp * ec.n_pairs + p] = e;
         if (out_count && lane == 0) out_count[(int64_t)hyp * ec.n_pairs + p] = cnt;
         wave_acc += (double)e;
