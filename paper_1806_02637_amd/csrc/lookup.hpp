@@ -148,11 +148,17 @@ __device__ __forceinline__ float g_angle_rows(float ax, float ay, float rinv, bo
 __device__ __forceinline__ double g_angle(double ax, double ay, double, bool xneg) {
     const double mx = fmax(ax, ay), mn = fmin(ax, ay);
     const bool swap = ay > ax;
-    const double z = mn / mx;
+    // min / max by the hardware reciprocal and two Newton steps (to the last
+    // bits of FP64; a correctly rounded division is not needed here)
+    double r = __builtin_amdgcn_rcp(mx);
+    r = fma(r, fma(-mx, r, 1.0), r);
+    r = fma(r, fma(-mx, r, 1.0), r);
+    const double z = mn * r;
     const double z2 = z * z;
-    double p = kAtan64[15];
+    constexpr int kN = sizeof(kAtan64) / sizeof(kAtan64[0]);
+    double p = kAtan64[kN - 1];
 #pragma unroll
-    for (int i = 14; i >= 0; --i) p = fma(p, z2, kAtan64[i]);
+    for (int i = kN - 2; i >= 0; --i) p = fma(p, z2, kAtan64[i]);
     const double off = swap ? 1.5707963267948966 : (xneg ? 3.141592653589793 : 0.0);
     return fma(swap != xneg ? -z : z, p, off);
 }
