@@ -14,7 +14,7 @@
   (N_kappa < K).
 
 Each row holds, per pair: e (Eqs. 15-16 with c = inf, so e = d), N_kappa
-(the planes whose lines hit both detectors) and the pair's scale
+(the planes whose lines meet both detectors) and the pair's scale
 (1/2) mean over those planes of (S_a^2 + S_b^2), against which per-pair
 differences are measured (e itself tends to 0 on consistent data).  The
 images come from the seeded input generator; every value from ``oracle``.
