@@ -518,9 +518,27 @@ def measure_gather_peaks(iters=1024, n_blocks=4096, reps=5):
             m = float(np.median(ms))
             out[f"{name}_{pname}_gbs"] = gathered / (m * 1e-3) / 1e9
         del buf
+    # the streaming rate HBM delivers: a 1 GiB device-to-device copy (read +
+    # write bytes / time), median of `reps`
+    n_copy = 1 << 28
+    src = torch.ones(n_copy, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    out["hbm_copy_gbs"] = 8.0 * n_copy / (float(np.median(ms)) * 1e-3) / 1e9
+    del src, dst
     torch.cuda.empty_cache()
     out.update(buffer_bytes={n: b for n, b in GATHER_LEVELS}, gathered_bytes_per_launch=gathered,
-               note="16-byte loads, 4 in flight per lane, 4096 x 256 threads")
+               note="16-byte loads, 4 in flight per lane, 4096 x 256 threads; hbm_copy_gbs: a 1 GiB "
+                    "device-to-device copy, bytes read + written per second")
     return out
 
 
@@ -783,6 +801,9 @@ def main():
         _log("gather peaks (L2, Infinity Cache, HBM)")
         peaks = measure_gather_peaks()
         rec["gather_peaks"] = peaks
+        # the roofline at the bandwidth a plain copy achieves on this GPU
+        rec["roofline"]["hbm_copy_gbs_measured"] = peaks["hbm_copy_gbs"]
+        rec["roofline"]["frac_vs_copy"] = achieved / peaks["hbm_copy_gbs"]
     else:
         peaks = None
     if kc:
