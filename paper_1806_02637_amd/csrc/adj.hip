@@ -92,6 +92,45 @@ __device__ __forceinline__ float kappa_sum(const G h[6], const float gH[6]) {
 }
 
 
+// Sums of 16 per-lane values over the wave at once, in a fixed order:
+// swap-and-add across the wave's halves (v_permlane32_swap: a value's lanes
+// 32-63 trade places with another's lanes 0-31, so one add leaves value i in
+// lanes 0-31 and value i + 8 in lanes 32-63, each summed over lanes l and
+// l + 32), the same within each half (v_permlane16_swap), then across 8 and
+// 4 lanes of a row (DPP rotate by 8, half-row mirror, the lane's bit choosing
+// which value it keeps) and over each quad.  Every lane ends with the total
+// of value ((l >> 2) & 1) + 2 ((l >> 3) & 1) + 4 (l >> 4): 35 instructions
+// for 16 totals where 16 separate wave sums take about 110.
+__device__ __forceinline__ float swap_add32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float wave_sum16(const float v[16], int lane) {
+    float w[8], x[4], y[2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = swap_add32(v[i], v[i + 8]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = swap_add16(w[i], w[i + 4]);
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b3 ? x[i + 2] : x[i], give = b3 ? x[i] : x[i + 2];
+        y[i] = keep + __int_as_float(dpp_i<0x128, 0xF>(__float_as_int(give)));  // row_ror:8
+    }
+    const float keep = b2 ? y[1] : y[0], give = b2 ? y[0] : y[1];
+    float z = keep + __int_as_float(dpp_i<0x141, 0xF>(__float_as_int(give)));  // row_half_mirror
+    z += __int_as_float(dpp_i<0xB1, 0xF>(__float_as_int(z)));                  // quad_perm [1,0,3,2]
+    z += __int_as_float(dpp_i<0x4E, 0xF>(__float_as_int(z)));                  // quad_perm [2,3,0,1]
+    return z;
+}
+__device__ __forceinline__ int wave_sum16_index(int lane) {
+    return ((lane >> 2) & 1) | (((lane >> 3) & 1) << 1) | ((lane >> 4) << 2);
+}
+
 // Cost and the pair sensitivities in one sweep over the planes.  With
 // d = sum (S_a - S_b)^2 / N, e = d / (1 + d / c), every plane's gradient
 // term is (2 / (N den^2)) (S_a - S_b) d(S_a - S_b), den = 1 + d / c: the
@@ -182,11 +221,12 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         const float e = ec.inv_c > 0.0f ? d * __builtin_amdgcn_rcpf(den) : d;
         wave_acc += (double)e;
         const float coef = cnt > 0 ? 2.0f * __builtin_amdgcn_rcpf((float)cnt * den * den) : 0.0f;
-        for (int i = 0; i < kSens; ++i) g[i] = coef * wave_sum(g[i]);
-        if (lane == 0) {
-            float *out = sens + ((int64_t)hyp * ec.n_pairs + p) * kSens;
-            for (int i = 0; i < kSens; ++i) out[i] = g[i];
-        }
+        float g16[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g16[i] = i < kSens ? g[i] : 0.0f;
+        const float gs = coef * wave_sum16(g16, lane);
+        const int j = wave_sum16_index(lane);
+        if ((lane & 3) == 0 && j < kSens) sens[((int64_t)hyp * ec.n_pairs + p) * kSens + j] = gs;
     }
     if (Q == 1) {
         if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
