@@ -100,7 +100,9 @@ __device__ __forceinline__ float kappa_sum(const G h[6], const float gH[6]) {
 // 4 lanes of a row (DPP rotate by 8, half-row mirror, the lane's bit choosing
 // which value it keeps) and over each quad.  Every lane ends with the total
 // of value ((l >> 2) & 1) + 2 ((l >> 3) & 1) + 4 (l >> 4): 35 instructions
-// for 16 totals where 16 separate wave sums take about 110.
+// for 16 totals where 16 separate wave sums take about 110.  All 64 lanes
+// must be active (the adjoint calls it after the plane loop, outside any
+// lane-dependent branch).
 __device__ __forceinline__ float swap_add32(float a, float b) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
