@@ -807,7 +807,12 @@ def main():
     else:
         peaks = None
     if kc:
-        rec["roofline"]["binding"] = binding_fractions(kc, per_call_ms, peaks)
+        b = rec["roofline"]["binding"] = binding_fractions(kc, per_call_ms, peaks)
+        # the resource that binds: the largest of the measured fractions
+        ranked = sorted([("VALU issue", b["valu_busy"]), ("L1 waiting on L2 data", b["l1_waiting_on_l2"]),
+                         ("L2 line bandwidth (measured peak)", b["l2_frac"]), ("HBM bandwidth", b["hbm_measured_frac"])],
+                        key=lambda kv: -kv[1])
+        rec["roofline"]["binds"] = ", then ".join(f"{k} ({v:.2f})" for k, v in ranked[:2])
     # per-pair values for the oracle check; only with the CPU baseline, whose
     # pass supplies the oracle's values (extra launches would also mix into
     # profiler averages of the timed kernel)
