@@ -154,15 +154,18 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
     const int64_t total = plane_work_items(ec.B, n_tiles);
     const int64_t w = xcd_work_item(total);
     if (w >= total) return;  // whole workgroups
-    const int tile = (int)(w / hyp_groups);
+    const int S = pair_subtiles(ec.B);
+    const int tile_w = (int)(w / hyp_groups);  // work tile: sub-tile sub of pair tile tile
+    const int tile = tile_w / S, sub = tile_w % S;
     const int hyp = (int)(w % hyp_groups) * hpb + wave % hpb;
-    const int part = wave / hpb, q_per = kPairsPerWave / Q;
+    const int part = wave / hpb, q_per = kPairsPerWave / (Q * S);
+    const int q0 = sub * (kPairsPerWave / S) + part * q_per;  // this wave's pairs: q0 .. q0 + q_per - 1
     // a wave without a hypothesis exists only when Q = 1, where no barrier
     // follows; with Q > 1 every wave has one (hpb <= B)
     if (hyp >= ec.B) return;
     __shared__ double part_acc[kWavesPerBlock];
     __shared__ PairConst<G> slots[kWavesPerBlock][kPairsPerWave];
-    stage_tile(slots[wave], table + (int64_t)hyp * ec.n_pairs, tile, lane, ec.n_views);
+    stage_tile(slots[wave], table + (int64_t)hyp * ec.n_pairs, tile, q0, q_per, lane, ec.n_views);
 
     const Tap *base = (const Tap *)sino;
     const float kinv = 1.0f / (float)ec.K;
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
     const bool in_tail = lane < (ec.K & 63);
     const uint64_t tail_mask = (1ull << (ec.K & 63)) - 1;
     double wave_acc = 0.0;
-    for (int q = part * q_per; q < (part + 1) * q_per; ++q) {
+    for (int q = 0; q < q_per; ++q) {
         const PairConst<G> pc = uniform(slots[wave][q]);
         if (pc.va < 0) continue;
         const int64_t p = pair_index(pc.va, pc.vb, ec.n_views);
@@ -231,14 +234,14 @@ __global__ __launch_bounds__(256) void ecc_adj_kernel(const void *__restrict__ s
         if ((lane & 3) == 0 && j < kSens) sens[((int64_t)hyp * ec.n_pairs + p) * kSens + j] = gs;
     }
     if (Q == 1) {
-        if (lane == 0) partials[(int64_t)hyp * n_tiles + tile] = wave_acc;
+        if (lane == 0) partials[(int64_t)hyp * n_tiles + tile_w] = wave_acc;
     } else {
         if (lane == 0) part_acc[wave] = wave_acc;
         __syncthreads();
         if (part == 0 && lane == 0) {
             double sum = 0.0;
             for (int k = 0; k < Q; ++k) sum += part_acc[k * hpb + wave];
-            partials[(int64_t)hyp * n_tiles + tile] = sum;
+            partials[(int64_t)hyp * n_tiles + tile_w] = sum;
         }
     }
 }

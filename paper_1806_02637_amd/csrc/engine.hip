@@ -136,6 +136,9 @@ int n_tiles_for(int n_views) {
     const int nb = (n_views + 7) / 8;  // 8-view blocks, tiles = block pairs I <= J
     return nb * (nb + 1) / 2;
 }
+// Work tiles of the plane kernels (pair tiles, each cut into
+// pair_subtiles(B) parts): one FP64 partial sum per hypothesis and work tile.
+int n_work_tiles(int n_views, int B) { return n_tiles_for(n_views) * pair_subtiles(B); }
 
 // Workspace layout of an evaluation.
 struct Workspace {
@@ -153,7 +156,7 @@ Workspace workspace_layout(const Scan *s, int B, bool grad) {
     w.table_off = off;  // sized for the FP64 plane-geometry form, the larger one
     off += align256(pair_const_bytes(true) * (uint64_t)B * n_pairs);
     w.part_off = off;
-    off += align256(sizeof(double) * (uint64_t)B * n_tiles_for(s->n_views));
+    off += align256(sizeof(double) * (uint64_t)B * n_work_tiles(s->n_views, B));
     w.sens_off = off;
     if (grad) off += align256(sizeof(float) * 14ull * (uint64_t)B * n_pairs);  // per-pair sensitivities
     w.pgrad_off = off;
@@ -716,7 +719,7 @@ static ecc_status cost_impl(ecc_ctx *ctx, int32_t scan_id, int32_t B, const doub
     ViewGeom *vt = (ViewGeom *)(ws + w.vt_off);
     double *partials = (double *)(ws + w.part_off);
     const EvalConsts ec = make_consts(s, B, params);
-    const int n_tiles = n_tiles_for(ec.n_views);
+    const int n_tiles = n_work_tiles(ec.n_views, B);
     void *table = ws + w.table_off;
     HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, nullptr, hs));
     HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs, pinv_dev));
@@ -776,7 +779,7 @@ ecc_status ecc_cost_grad(ecc_ctx *ctx, int32_t scan_id, int32_t B, const double 
     double *partials = (double *)(ws + w.part_off);
     float *pgrad = out_pair_grad_dev ? out_pair_grad_dev : (float *)(ws + w.pgrad_off);
     const EvalConsts ec = make_consts(s, B, params);
-    const int n_tiles = n_tiles_for(ec.n_views);
+    const int n_tiles = n_work_tiles(ec.n_views, B);
     void *table = ws + w.table_off;
     HIP_TRY(launch_view_setup(s->P_dev, s->intr_dev, theta_dev, B, s->n_views, vt, vg, hs));
     HIP_TRY(launch_pair_setup(s->scale_dev, vt, ec, table, hs));

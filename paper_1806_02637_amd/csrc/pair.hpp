@@ -145,17 +145,20 @@ __device__ __forceinline__ bool tile_pair(int tile, int q, int n_views, int &a, 
     return a < n_views && b < n_views;
 }
 
-// Stages the constants of every pair of a tile into this wave's LDS slots
-// (lane q loads pair q); empty slots get va = -1.  Wave-scope fences make the
-// slots written by one lane visible to the whole wave.
+// Stages the constants of pairs q0 .. q0 + n - 1 of a tile into this wave's
+// LDS slots (lane i < n loads pair q0 + i into slot i); empty slots get
+// va = -1.  Wave-scope fences make the slots written by one lane visible to
+// the whole wave.
 template <class G>
-__device__ __forceinline__ void stage_tile(PairConst<G> *slots, const PairConst<G> *tab, int tile, int lane,
-                                           int n_views) {
-    int a, b;
-    if (tile_pair(tile, lane, n_views, a, b)) {
-        slots[lane] = tab[pair_index(a, b, n_views)];
-    } else {
-        slots[lane].va = -1;
+__device__ __forceinline__ void stage_tile(PairConst<G> *slots, const PairConst<G> *tab, int tile, int q0, int n,
+                                           int lane, int n_views) {
+    if (lane < n) {
+        int a, b;
+        if (tile_pair(tile, q0 + lane, n_views, a, b)) {
+            slots[lane] = tab[pair_index(a, b, n_views)];
+        } else {
+            slots[lane].va = -1;
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -174,9 +177,9 @@ __device__ __forceinline__ void stage_tile(PairConst<G> *slots, const PairConst<
 // step) has four times the waves in flight it would have with one wave per
 // tile.
 __host__ __device__ inline int pair_split(int) { return kWavesPerBlock; }
-__host__ __device__ inline int64_t plane_work_items(int B, int n_tiles) {
+__host__ __device__ inline int64_t plane_work_items(int B, int n_work_tiles) {
     const int hpb = kWavesPerBlock / pair_split(B);
-    return (int64_t)n_tiles * ((B + hpb - 1) / hpb);
+    return (int64_t)n_work_tiles * ((B + hpb - 1) / hpb);
 }
 
 // Static LDS of the plane kernels: the pair constants of each wave's tile and
