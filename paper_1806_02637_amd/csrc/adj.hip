@@ -2,7 +2,8 @@
 // motion parameters, with the line geometry recomputed rather than stored.
 //
 // ecc_adj       same work split as the forward kernel (one hypothesis x one
-//               pair tile per workgroup, 16 pairs per wave).  Per pair:
+//               work tile per workgroup, its pairs shared by the four
+//               waves).  Per pair:
 //                 1. forward sweep over the K planes -> d, N (Eq. 15), e (Eq. 16);
 //                 2. reverse sweep over the planes: dE/dS_a = +g, dE/dS_b = -g with
 //                    g = de/dd * 2 (S_a - S_b) / N on planes hitting both

@@ -5,8 +5,8 @@
 // pair_setup   one thread per (hypothesis, pair): the pair's geometry in FP64
 //              (baseline, pencil of planes, the two line maps of Eq. 14) ->
 //              a table of per-plane constants.
-// ecc_fwd      a workgroup = one hypothesis x one tile of up to 64 view
-//              pairs (8 x 8 view blocks), 16 pairs per wave; a wave walks its
+// ecc_fwd      a workgroup = one hypothesis x one sub-tile of a tile of up
+//              to 64 view pairs (8 x 8 view blocks); a wave walks its
 //              pairs (constants staged in LDS) with lanes along the plane angle kappa: line ->
 //              (alpha, t) -> four bilinear taps per view in one load ->
 //              (S_a - S_b)^2 -> wave-shuffle sum (Eq. 15) -> Cauchy norm
@@ -184,9 +184,10 @@ __device__ __forceinline__ void combine_plane(const PlaneInFlight<Tap> &P, bool 
     cnt += __popcll(P.mask & count_mask);
 }
 
-// A workgroup = one hypothesis x one pair tile, the tile's 64 pairs split
-// into 4 parts over its waves (pair_split); consecutive workgroups are the
-// same tile's other hypotheses, which read nearly the same sinogram cells.  Lanes
+// A workgroup = one hypothesis x one work tile (a sub-tile of a pair tile,
+// pair_subtiles), its pairs split into 4 parts over its waves (pair_split);
+// consecutive workgroups are the same work tile's other hypotheses, which
+// read nearly the same sinogram cells.  Lanes
 // walk the planes k = lane + 64 i; the trip count is wave-uniform (K / 64
 // full sweeps plus a masked tail) and the hit count is a population count of
 // the hit mask.  The gathers of sweep i + 1 are issued before sweep i is

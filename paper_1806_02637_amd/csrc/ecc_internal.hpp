@@ -141,15 +141,16 @@ constexpr int kPairsPerWave = 64;
 // zero border (pixels) around the weighted projections read by the line sums
 constexpr int kImgPad = 3;
 constexpr int kWavesPerBlock = 4;
-// Sub-tiles per pair tile: with one or two hypotheses a tile's 64 pairs are
-// spread over 8 or 4 consecutive workgroups (8 or 16 pairs each), so that
-// an XCD keeps few tiles in flight (at B = 1 on the 496-view scan, 1953
-// whole tiles put about 1000 different tiles' lines in flight and the L2 hit
-// 40 % of requests; 4 sub-tiles per tile cut a B = 1 cost from 0.64 to 0.49
-// ms, 8 to 0.45 ms).  The plane kernels take the number of work tiles, pair
-// tiles * pair_subtiles(B), and write one partial sum per hypothesis and
-// work tile.
-__host__ __device__ inline int pair_subtiles(int B) { return B == 1 ? 8 : (B == 2 ? 4 : 1); }
+// Sub-tiles per pair tile: a tile's 64 pairs are spread over 8 consecutive
+// workgroups with one hypothesis (8 pairs each), 4 with two, 2 otherwise (32
+// pairs each), so that an XCD keeps few tiles' lines in flight.  At B = 1 on
+// the 496-view scan 1953 whole tiles put about 1000 different tiles' lines
+// in flight and the L2 hit 40 % of requests; 4 sub-tiles per tile cut a
+// B = 1 cost from 0.64 to 0.49 ms, 8 to 0.45 ms; at B = 32, 2 sub-tiles
+// take 1 % off the forward step and 2 % off cost + gradient (4 are no
+// better).  The plane kernels take the number of work tiles, pair tiles *
+// pair_subtiles(B), and write one partial sum per hypothesis and work tile.
+__host__ __device__ inline int pair_subtiles(int B) { return B == 1 ? 8 : (B == 2 ? 4 : 2); }
 // caps on resident plane-kernel workgroups per CU (0 = no cap), 4 for the
 // forward kernel with every storage form and for the adjoint (at B = 32 on
 // the 496-view scan: the FP32 forward kernel at 3 is 2 % slower, the 16-bit

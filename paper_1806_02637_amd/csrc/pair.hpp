@@ -165,11 +165,12 @@ __device__ __forceinline__ void stage_tile(PairConst<G> *slots, const PairConst<
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Waves of a workgroup: kWavesPerBlock / Q hypotheses of one pair tile, each
-// tile's pairs split into Q parts, Q = pair_split(B); the parts' sums are
-// added in a fixed order.  Q = kWavesPerBlock for every B: a workgroup is one
-// hypothesis of one tile, its waves taking 16 pairs each, and consecutive
-// workgroups on an XCD are the same tile's next hypotheses.  The XCD then
+// Waves of a workgroup: kWavesPerBlock / Q hypotheses of one work tile (a
+// pair tile's sub-tile, pair_subtiles), its pairs split into Q parts,
+// Q = pair_split(B); the parts' sums are added in a fixed order.
+// Q = kWavesPerBlock for every B: a workgroup is one hypothesis of one work
+// tile, its waves sharing the work tile's pairs, and consecutive workgroups
+// on an XCD are the same work tile's next hypotheses.  The XCD then
 // holds all hypotheses of a few tiles rather than four hypotheses of many, a
 // smaller set of sinogram lines in flight (at B = 32 on the 496-view scan the
 // forward kernel ran 2-4 % and the adjoint 7 % faster than with four
