@@ -177,8 +177,8 @@ __device__ __forceinline__ void issue_plane(PlaneInFlight<Tap> &P, const PairCon
 template <class Tap>
 __device__ __forceinline__ void combine_plane(const PlaneInFlight<Tap> &P, bool valid, uint64_t count_mask,
                                               float &acc, int &cnt) {
-    const float Ua = P.w_a * bilerp(Tap::unpack(P.ta), P.fa_a, P.ft_a);
-    const float Ub = P.w_b * bilerp(Tap::unpack(P.tb), P.fa_b, P.ft_b);
+    const float Ua = P.w_a * bilinear<Tap>(P.ta, P.fa_a, P.ft_a);
+    const float Ub = P.w_b * bilinear<Tap>(P.tb, P.fa_b, P.ft_b);
     const float d = (P.hit & valid) ? Ua - (P.flip ? -Ub : Ub) : 0.0f;
     acc = fmaf(d, d, acc);
     cnt += __popcll(P.mask & count_mask);

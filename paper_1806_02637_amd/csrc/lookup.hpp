@@ -110,8 +110,9 @@ struct TapF16 {
 // FP32: fitted polynomials (poly_coeffs.hpp) -- the plane angle only selects
 // which plane of the pencil is sampled, identically for both views, and the
 // line angle enters the lookup through an FP32 fraction anyway.  FP64: the
-// library sincos (once per lane and pair), a 16-term fitted atan (2e-14 rad)
-// and a Newton-refined reciprocal square root.
+// library sincos (once per lane and pair), a 13-term fitted atan (3.5e-12
+// rad) of min / max by the hardware reciprocal with two Newton steps, and a
+// Newton-refined reciprocal square root.
 __device__ __forceinline__ void g_sincos(float x, float *s, float *c) {
     // |x| <= pi/2 (plane angles of the pencil)
     const float x2 = x * x;
@@ -298,6 +299,38 @@ __device__ __forceinline__ typename Tap::Raw fetch_taps(const LineCoord<G> &c, c
 __device__ __forceinline__ float bilerp(const Taps &tp, float fa, float ft) {
     const float r0 = fmaf(ft, tp.s01 - tp.s00, tp.s00);
     const float r1 = fmaf(ft, tp.s11 - tp.s10, tp.s10);
+    return fmaf(fa, r1 - r0, r0);
+}
+
+// s1 - s0 for the FP16 values in the low (HI = false) or high halves of two
+// 32-bit words, in FP32 with one rounding: v_fma_mix_f32 reads FP16 operands
+// in place (op_sel picks the half), computing s1 * 1 + (-s0).
+template <bool HI>
+__device__ __forceinline__ float f16_sub(uint32_t w1, uint32_t w0) {
+    float d;
+    if constexpr (HI)
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(d) : "v"(w1), "v"(w0));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(d) : "v"(w1), "v"(w0));
+    return d;
+}
+
+// Bilinear value from a cell's raw loaded words.  FP32 and BF16 convert the
+// taps first.  FP16 takes the t-differences by f16_sub straight from the
+// loaded words (an FP16 value converts to FP32 exactly, so these are the
+// same operations and roundings as bilerp on the converted taps) and
+// converts only the two taps at t: two conversions per view instead of four.
+template <class Tap>
+__device__ __forceinline__ float bilinear(const typename Tap::Raw &v, float fa, float ft) {
+    return bilerp(Tap::unpack(v), fa, ft);
+}
+template <>
+__device__ __forceinline__ float bilinear<TapF16>(const TapF16::Raw &v, float fa, float ft) {
+    // v.x = (S[m][k], S[m+1][k]), v.y = (S[m][k+1], S[m+1][k+1]) as (low, high) halves
+    const float s00 = (float)__builtin_bit_cast(_Float16, (uint16_t)(v.x & 0xFFFFu));
+    const float s10 = (float)__builtin_bit_cast(_Float16, (uint16_t)(v.x >> 16));
+    const float r0 = fmaf(ft, f16_sub<false>(v.y, v.x), s00);
+    const float r1 = fmaf(ft, f16_sub<true>(v.y, v.x), s10);
     return fmaf(fa, r1 - r0, r0);
 }
 
