@@ -178,15 +178,13 @@ __device__ __forceinline__ float g_clamp(float x, float lo, float hi) { return _
 __device__ __forceinline__ double g_clamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 
 // Grid cell of a coordinate x: returns the fraction x - floor(x) and sets i =
-// floor(x) clamped to [0, hi].  Lanes whose line hits a detector have x in
-// [0, hi + 1), where the two agree; on the others the clamp only keeps the
-// address in range (the FP32 convert-with-floor gives 0 for NaN and
-// saturates infinities).
-__device__ __forceinline__ float cell_split(float x, float hi, int &i) {
-    // clamp (a NaN input yields 0 or NaN), then floor and convert in one
-    // instruction, which turns NaN into 0
-    const float xc = __builtin_amdgcn_fmed3f(x, 0.0f, hi);
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(xc));
+// floor(x).  Lanes whose line hits a detector have x in [0, hi + 1) (rows
+// alpha / dalpha <= n_alpha, columns tau in [1, n_t] since |t| <= t_max).
+// FP32 leaves i unclamped -- floor and convert in one instruction, NaN -> 0,
+// infinities saturate -- and tap_address bounds the byte offset instead;
+// FP64 clamps i to [0, hi].
+__device__ __forceinline__ float cell_split(float x, float, int &i) {
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(x));
     return __builtin_amdgcn_fractf(x);
 }
 __device__ __forceinline__ float cell_split(double x, double hi, int &i) {
@@ -276,13 +274,19 @@ __device__ __forceinline__ uint64_t hit_mask(const LineCoord<G> &c) {
     return g_cmp_gt(c.r2, (G)0) & g_cmp_le(fabs(c.l3), c.edge);
 }
 
-// The four taps of a line's bilinear cell.  A view holds < 2^28 elements, so
-// the byte offset is a 32-bit value added to the view's base address, and
-// m, j < 2^24 allow the 24-bit multiply-add.
+// The four taps of a line's bilinear cell: elements e and e + 1 of the view,
+// e = m * row_elems + j.  A view holds < 2^28 elements of <= 8 bytes, so the
+// byte offset is a 32-bit value added to the view's base address.  On lanes
+// that hit a detector 0 <= m <= n_alpha and 0 <= j <= n_t, so e <= view_elems
+// - 2 and the 24-bit multiply is exact.  FP32 leaves the indices of the other
+// lanes unclamped (possibly negative or saturated): their offset wraps, and
+// one unsigned minimum keeps the load inside the view -- a valid cell whose
+// value is discarded.  FP64 indices are clamped already.
 template <class Tap, class G>
 __device__ __forceinline__ const Tap *tap_address(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec) {
-    const uint32_t e = __umul24((uint32_t)c.m, (uint32_t)ec.row_elems) + (uint32_t)c.j;
-    return (const Tap *)((const char *)sview + e * (uint32_t)sizeof(Tap));
+    uint32_t off = (__umul24((uint32_t)c.m, (uint32_t)ec.row_elems) + (uint32_t)c.j) * (uint32_t)sizeof(Tap);
+    if constexpr (sizeof(G) == 4) off = min(off, (uint32_t)(ec.view_elems - 2) * (uint32_t)sizeof(Tap));
+    return (const Tap *)((const char *)sview + off);
 }
 template <class Tap, class G>
 __device__ __forceinline__ Taps load_taps(const LineCoord<G> &c, const Tap *sview, const EvalConsts &ec) {
