@@ -109,3 +109,34 @@ def test_saturating_cauchy(eng):
         assert abs(got[h] - ref) <= 1e-5 * ref
         assert ref <= 10 * c + 1e-12  # 10 pairs, each e < c
     scan.free()
+
+
+def test_views_moved_far_off_the_scan(eng):
+    """Two views moved 1 m and 100 m sideways: many of their pairs' lines
+    miss a detector by far (|t| up to 603 px against t_max = 90.5 px), so
+    the kernels' column indices for those lanes run past the sinogram row and
+    past the view -- those lanes must read nothing that counts.  Per pair, e
+    and the plane count N agree with the oracle (counts exactly: every plane
+    of these pairs is at least 1 % of the edge distance |t| - edge from the
+    hit-test boundary, far beyond FP32 rounding)."""
+    _say("case: edges views moved 1 m and 100 m (lines far off the detectors)")
+    g, P, intr, grid, sino, scan = _scan(eng, 5, 11)
+    th = np.zeros((2, 5, 6))
+    for h, shift in enumerate((1e3, 1e5)):
+        th[h, 1, 3] = shift
+        th[h, 3, 4] = -shift / 3
+    params = oracle.EccParams(64, g.default_object_radius())
+    cost, pairs, counts = scan.cost(th, 64, params.R_mm, with_pairs=True, with_counts=True)
+    cost, pairs, counts = cost.cpu().numpy(), pairs.cpu().numpy(), counts.cpu().numpy()
+    for h in range(2):
+        _say(f"  hyp {h}: {cost[h]:.6e}, N = {counts[h].tolist()}")
+        for a in range(5):
+            for b in range(a + 1, 5):
+                e_ref, _, n_ref = ecc_pair(as_rows(P[a]), as_rows(P[b]), list(th[h, a]), list(th[h, b]), intr[a],
+                                           intr[b], grid, sino, a, b, params)
+                p = pair_index(a, b, 5)
+                assert counts[h, p] == n_ref, (h, a, b, counts[h, p], n_ref)
+                assert abs(pairs[h, p] - e_ref) <= 2e-4 * e_ref + 1e-5 * pairs[h].max(), (h, a, b, pairs[h, p], e_ref)
+        ref = oracle.ecc_cost(P, intr, th[h], grid, sino, params)[0]
+        assert abs(cost[h] - ref) <= 1e-5 * ref
+    scan.free()
