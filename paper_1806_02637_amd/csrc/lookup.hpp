@@ -146,6 +146,18 @@ __device__ __forceinline__ float g_angle_rows(float ax, float ay, float rinv, bo
     const float off = swap ? ec.rows_half_pi : (xneg ? ec.rows_pi : 0.0f);
     return fmaf(swap != xneg ? -s : s, p, off);
 }
+// The same angle for a line steeper than 45 degrees (|y| > |x|) from the
+// signed cosine u = x / |(x, y)|: pi/2 - asin(u).  |u| and u^2 round as s
+// and s^2 above and -u carries the sign the general form selects, so the two
+// give the same bits on such lines.
+template <int NT>
+__device__ __forceinline__ float g_angle_rows_steep(float u, const EvalConsts &ec) {
+    const float u2 = u * u;
+    float p = ec.asin_rows[NT - 1];
+#pragma unroll
+    for (int i = NT - 2; i >= 0; --i) p = fmaf(p, u2, ec.asin_rows[i]);
+    return fmaf(-u, p, ec.rows_half_pi);
+}
 __device__ __forceinline__ double g_angle(double ax, double ay, double, bool xneg) {
     const double mx = fmax(ax, ay), mn = fmin(ax, ay);
     const bool swap = ay > ax;
@@ -222,6 +234,14 @@ struct LineCoord {
     bool hit, fold;      // fold: the line was negated (sign -1 on S)
 };
 
+// The hit test as a wave mask (inactive lanes read 0): the ballot of the
+// per-lane decision reuses its compare, so masks taken before and after a
+// branch cost no second comparison.
+template <class G>
+__device__ __forceinline__ uint64_t hit_mask(const LineCoord<G> &c) {
+    return __builtin_amdgcn_ballot_w64(c.hit);
+}
+
 template <class G, int NT = 7>
 __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, const EvalConsts &ec) {
     LineCoord<G> c;
@@ -238,19 +258,31 @@ __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, con
     const G r2 = l1 * l1 + l2 * l2;
     c.r2 = r2;
     c.rinv = g_rsqrt(r2);
-    // the folded l1 is negative iff exactly one of (l1 < 0, fold) holds; at
-    // l1 = 0 both quadrant choices give pi/2
-    const bool xneg = (l1 < (G)0) != fold;
-    G rows;  // alpha / dalpha
-    if constexpr (sizeof(G) == 4)
-        rows = g_angle_rows<NT>(fabs(l1), fabs(l2), c.rinv, xneg, ec);
-    else
-        rows = g_angle(fabs(l1), fabs(l2), c.rinv, xneg) * GConst<G>::inv_dalpha(ec);
-    const G t = -c.l3 * c.rinv;
+    // 1 / r with the fold's sign: t and the folded cosine without flipping
+    // the line itself (negation is exact, so t = -l3_folded / r bit for bit)
+    const G rinv_f = g_flip(c.rinv, fold);
+    const G t = -l3 * rinv_f;
     // closed detector rectangle of pixel edges:
     // |t| <= (W/2)|cos a| + (H/2)|sin a|  <=>  |l3| <= (W/2)|l1| + (H/2)|l2|
     c.edge = (G)ec.half_w * fabs(l1) + (G)ec.half_h * fabs(l2);
     c.hit = (r2 > (G)0) & (fabs(l3) <= c.edge);
+    // the folded l1 is negative iff exactly one of (l1 < 0, fold) holds; at
+    // l1 = 0 both quadrant choices give pi/2
+    const bool xneg = (l1 < (G)0) != fold;
+    G rows;  // alpha / dalpha
+    if constexpr (sizeof(G) == 4) {
+        // Lanes walk consecutive planes, whose lines turn slowly: in most
+        // sweeps every lane that hits has a line steeper than 45 degrees and
+        // the wave takes the steep form (no quadrant selects); a wave with
+        // any hitting lane at or below 45 degrees takes the general form.
+        // Lanes that miss may take either: their sample is discarded.
+        if (__builtin_amdgcn_ballot_w64(c.hit & (fabs(l2) <= fabs(l1))) == 0)
+            rows = g_angle_rows_steep<NT>(l1 * rinv_f, ec);
+        else
+            rows = g_angle_rows<NT>(fabs(l1), fabs(l2), c.rinv, xneg, ec);
+    } else {
+        rows = g_angle(fabs(l1), fabs(l2), c.rinv, xneg) * GConst<G>::inv_dalpha(ec);
+    }
     // alpha <= pi (rounded up by at most an ulp) puts row m <= n_alpha: the
     // stored cell rows run to n_alpha, whose upper row continues the
     // sinogram past pi
@@ -263,16 +295,6 @@ __device__ __forceinline__ LineCoord<G> line_coord(const G h[6], G cs, G sn, con
     return c;
 }
 
-// The same hit test as a wave mask (the comparisons are shared with
-// LineCoord::hit; inactive lanes read 0).
-__device__ __forceinline__ uint64_t g_cmp_gt(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 2); }
-__device__ __forceinline__ uint64_t g_cmp_le(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 5); }
-__device__ __forceinline__ uint64_t g_cmp_gt(double a, double b) { return __builtin_amdgcn_fcmp(a, b, 2); }
-__device__ __forceinline__ uint64_t g_cmp_le(double a, double b) { return __builtin_amdgcn_fcmp(a, b, 5); }
-template <class G>
-__device__ __forceinline__ uint64_t hit_mask(const LineCoord<G> &c) {
-    return g_cmp_gt(c.r2, (G)0) & g_cmp_le(fabs(c.l3), c.edge);
-}
 
 // The four taps of a line's bilinear cell: elements e and e + 1 of the view,
 // e = m * row_elems + j.  A view holds < 2^28 elements of <= 8 bytes, so the
