@@ -184,8 +184,7 @@ __device__ __forceinline__ double g_rsqrt(double x) {
     return r;
 }
 
-// Clamp to [lo, hi]; the FP32 form is one median-of-three (a NaN input
-// yields lo or NaN, and NaN converts to index 0: addresses stay in range).
+// Clamp to [lo, hi]: one median-of-three in FP32; FP64 yields lo for a NaN.
 __device__ __forceinline__ float g_clamp(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 __device__ __forceinline__ double g_clamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 
@@ -230,7 +229,7 @@ struct LineCoord {
     G l1, l2, l3, rinv;  // folded line, 1/|(l1, l2)|
     G r2, edge;          // |(l1, l2)|^2, (W/2)|l1| + (H/2)|l2|
     float fa, ft, tf;    // bilinear fractions, folded t (FP32)
-    int m, j;            // cell: row m <= n_alpha, stored column j = k + 1 (clamped for memory safety)
+    int m, j;            // cell: row m, stored column j = k + 1 (in range on hitting lanes; see tap_address)
     bool hit, fold;      // fold: the line was negated (sign -1 on S)
 };
 

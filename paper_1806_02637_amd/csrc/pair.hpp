@@ -52,7 +52,8 @@ __device__ __forceinline__ void pair_setup(const ViewGeom &A, const ViewGeom &Bv
     if (ec.kappa_detector) {
         if (!pair_arc(Ha, Hb, (double)ec.half_w, (double)ec.half_h, lo, hi)) {
             // every sample at kappa = 0 on the line x = -2^20 px: off every
-            // detector, finite coordinates (clamped cell indices)
+            // detector, finite coordinates (cell indices outside the
+            // sinogram, whose loads tap_address keeps inside the view)
             for (int i = 0; i < 6; ++i) Ha[i] = Hb[i] = 0.0;
             Ha[0] = Hb[0] = 1.0;
             Ha[2] = Hb[2] = 1048576.0;
